@@ -1,0 +1,216 @@
+"""ctypes wrapper of the FP64 CPU oracle (``ct_oracle.c``).
+
+Test infrastructure only: the test suite, the smoke check and the CPU
+baseline leg of the benchmark load it.  It never imports the library package
+and the library never imports it; both consume the seeded inputs of
+``workloads``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ct_oracle.c")
+_LIB = os.path.join(_HERE, "libct_oracle.so")
+
+OK, EINVAL, EMAXSTEPS, ENONFINITE = 0, -1, -5, -6
+REPULSION, DRIFT, DIFFUSION = 1, 2, 4
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (IEEE FP64: no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-Wall", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class OcParams(C.Structure):
+    _fields_ = [
+        ("thickness_um", C.c_double), ("v_bias", C.c_double), ("v_dep", C.c_double),
+        ("temperature_k", C.c_double), ("pitch_um", C.c_double), ("grid_n", C.c_int32),
+        ("dt_ns", C.c_double), ("softening_um", C.c_double), ("eps_r", C.c_double),
+        ("pair_energy_ev", C.c_double), ("mobility", C.c_int32),
+        ("mu0_override", C.c_double), ("ec_override", C.c_double), ("beta_override", C.c_double),
+        ("physics", C.c_uint32), ("seed", C.c_uint64), ("max_steps", C.c_int64),
+    ]
+
+
+class OcEvent(C.Structure):
+    _fields_ = [
+        ("energy_kev", C.c_double), ("n_carriers", C.c_int32), ("n_deposits", C.c_int32),
+        ("sigma_um", C.c_double), ("deposits", C.POINTER(C.c_double)),
+        ("xyz", C.POINTER(C.c_double)), ("ids", C.POINTER(C.c_int32)), ("start_step", C.c_int64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = C.CDLL(_LIB)
+        dp, ip, up = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_uint32)
+        L.oc_philox4x32_10.argtypes = [up, up, up]
+        L.oc_normals3.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, dp]
+        L.oc_coulomb_k.argtypes = [C.POINTER(OcParams)]
+        L.oc_coulomb_k.restype = C.c_double
+        L.oc_thermal_voltage.argtypes = [C.POINTER(OcParams)]
+        L.oc_thermal_voltage.restype = C.c_double
+        L.oc_mobility_params.argtypes = [C.POINTER(OcParams), dp]
+        L.oc_mobility.argtypes = [C.POINTER(OcParams), C.c_double]
+        L.oc_mobility.restype = C.c_double
+        L.oc_drift_field.argtypes = [C.POINTER(OcParams), C.c_double]
+        L.oc_drift_field.restype = C.c_double
+        L.oc_field.argtypes = [C.POINTER(OcParams), C.c_int64, dp, dp]
+        L.oc_carrier_count.argtypes = [C.POINTER(OcParams), C.POINTER(OcEvent)]
+        L.oc_carrier_count.restype = C.c_int32
+        L.oc_initial_sigma.argtypes = [C.POINTER(OcEvent)]
+        L.oc_initial_sigma.restype = C.c_double
+        L.oc_pixel_bin.argtypes = [C.POINTER(OcParams), C.c_double, C.c_double]
+        L.oc_pixel_bin.restype = C.c_int32
+        L.oc_run.argtypes = [C.POINTER(OcParams), C.POINTER(OcEvent), C.c_int32, C.c_uint64,
+                             ip, dp, ip, C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]
+        L.oc_run.restype = C.c_int
+        L.oc_set_threads.argtypes = [C.c_int]
+        L.oc_get_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: Optional[np.ndarray]):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def params(sensor) -> OcParams:
+    flags = (REPULSION if sensor.repulsion else 0) | (DRIFT if sensor.drift else 0) | \
+            (DIFFUSION if sensor.diffusion else 0)
+    mob = {"jacoboni": 0, "constant": 1}[sensor.mobility]
+    return OcParams(sensor.thickness_um, sensor.v_bias, sensor.v_dep, sensor.temperature_k,
+                    sensor.pitch_um, sensor.grid_n, sensor.dt_ns, sensor.softening_um, sensor.eps_r,
+                    sensor.pair_energy_ev, mob, sensor.mu0_override, sensor.ec_override,
+                    sensor.beta_override, flags, sensor.seed, sensor.max_steps)
+
+
+def set_threads(n: int) -> None:
+    lib().oc_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(lib().oc_get_threads())
+
+
+def philox(ctr, key) -> np.ndarray:
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().oc_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def normals3(seed: int, c0: int, c1: int, c2: int, c3: int) -> np.ndarray:
+    o = (C.c_double * 3)()
+    lib().oc_normals3(seed, c0, c1, c2, c3, o)
+    return np.array(list(o))
+
+
+def coulomb_k(sensor) -> float:
+    return float(lib().oc_coulomb_k(C.byref(params(sensor))))
+
+
+def thermal_voltage(sensor) -> float:
+    return float(lib().oc_thermal_voltage(C.byref(params(sensor))))
+
+
+def mobility_params(sensor) -> tuple:
+    o = (C.c_double * 3)()
+    lib().oc_mobility_params(C.byref(params(sensor)), o)
+    return tuple(o)
+
+
+def mobility(sensor, e_mag: float) -> float:
+    return float(lib().oc_mobility(C.byref(params(sensor)), float(e_mag)))
+
+
+def drift_field(sensor, z: float) -> float:
+    return float(lib().oc_drift_field(C.byref(params(sensor)), float(z)))
+
+
+def pixel_bin(sensor, x: float, y: float) -> int:
+    return int(lib().oc_pixel_bin(C.byref(params(sensor)), float(x), float(y)))
+
+
+def field(sensor, xyz: np.ndarray) -> np.ndarray:
+    """Repulsion field (V/um) of the carriers at xyz [n, 3] on each other."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    E = np.zeros_like(xyz)
+    lib().oc_field(C.byref(params(sensor)), xyz.shape[0], _dp(xyz), _dp(E))
+    return E
+
+
+def _events(batch):
+    B = batch.n_events
+    evs = (OcEvent * max(B, 1))()
+    doff = batch.dep_offsets()
+    xo = 0
+    keep = []
+    for b in range(B):
+        nd = int(batch.n_deposits[b])
+        dep = np.ascontiguousarray(batch.deposits[doff[b]:doff[b + 1]]) if nd > 0 else None
+        xyz = None
+        if nd == 0:
+            n = int(batch.n_carriers[b])
+            xyz = np.ascontiguousarray(batch.xyz[xo:xo + n])
+            xo += n
+        keep += [dep, xyz]
+        evs[b] = OcEvent(float(batch.energy_kev[b]), int(batch.n_carriers[b]), nd,
+                         float(batch.sigma_um[b]), _dp(dep), _dp(xyz), None,
+                         int(batch.start_step[b]))
+    return evs, keep
+
+
+def carrier_counts(sensor, batch) -> np.ndarray:
+    evs, keep = _events(batch)
+    p = params(sensor)
+    return np.array([lib().oc_carrier_count(C.byref(p), C.byref(evs[b]))
+                     for b in range(batch.n_events)], dtype=np.int64)
+
+
+def initial_sigma(batch, b: int = 0) -> float:
+    evs, keep = _events(batch)
+    return float(lib().oc_initial_sigma(C.byref(evs[b])))
+
+
+def run(sensor, batch, threads: Optional[int] = None) -> dict:
+    """Simulate every event of the batch; returns the oracle's outputs."""
+    if threads is not None:
+        set_threads(threads)
+    p = params(sensor)
+    evs, keep = _events(batch)
+    n = carrier_counts(sensor, batch)
+    off = np.zeros(batch.n_events + 1, dtype=np.int64)
+    np.cumsum(np.maximum(n, 0), out=off[1:])
+    G1 = sensor.grid_n * sensor.grid_n + 1
+    pix = np.zeros((batch.n_events, G1), dtype=np.int32)
+    xyz = np.zeros((int(off[-1]), 3), dtype=np.float64)
+    cstep = np.zeros(int(off[-1]), dtype=np.int32)
+    steps = np.zeros(batch.n_events, dtype=np.int64)
+    pairs = C.c_uint64(0)
+    st = lib().oc_run(C.byref(p), evs, batch.n_events, batch.first_event_id,
+                      pix.ctypes.data_as(C.POINTER(C.c_int32)), _dp(xyz),
+                      cstep.ctypes.data_as(C.POINTER(C.c_int32)),
+                      steps.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(pairs))
+    return {"status": int(st), "pix": pix, "xyz": xyz, "cstep": cstep, "steps": steps,
+            "pairs": int(pairs.value), "offsets": off, "n": n}

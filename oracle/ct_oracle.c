@@ -1,0 +1,457 @@
+/*
+ * FP64 CPU oracle of the brute-force charge-transport Monte Carlo of
+ * Xie et al., "Optimization and validation of charge transport simulation
+ * for hybrid pixel detectors incorporating the repulsion effect"
+ * (arXiv:2506.09712): the comprehensive method of Sec. 2.1, Eqs. 2-6, as
+ * laid out in Appendix A, Algorithm 1.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * HIP library is checked against.  It shares no code, header or constant
+ * table with the library; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load it.  The product path never calls
+ * it.
+ *
+ * Conventions (units: micrometre, nanosecond, volt, kelvin):
+ *  - z is the distance from the pixel (collecting) plane; the paper's z
+ *    (measured from the entrance side, Eq. 6 and the limits of Eq. 9) is
+ *    H - z here.  Holes drift towards z = 0 and are collected once an update
+ *    leaves them at z <= 0.  An update that crosses the entrance side z = H
+ *    is mirrored back (z -> 2H - z).
+ *  - Repulsion field (Eq. 4, holes only, q_j = +e):
+ *        E_i = K * sum_{j != i, alive} (r_i - r_j) / (|r_i - r_j|^2 + s^2)^(3/2)
+ *    with K = e / (4 pi eps0 eps_r) and Plummer softening s (s = 0 is Eq. 4
+ *    exactly).  Eq. 4 prints q_i q_j, which is a force; the field acting on
+ *    a hole is the sum of q_j r_ij / (4 pi eps0 eps_r r^3).
+ *  - Drift field (Eq. 6, rewritten for this z axis):
+ *        E_z(z) = -[(Vb + Vd)/H - 2 Vd z / H^2]
+ *  - Mobility: Caughey-Thomas form mu = mu0 / (1 + (E/Ec)^beta)^(1/beta)
+ *    evaluated at |E_drift + E_rep| (Sec. 2.1, Algorithm 1), with the
+ *    Jacoboni-Canali hole temperature laws for mu0 = vm/Ec, Ec and beta.
+ *  - Diffusion: D = mu k T / e (Einstein relation, Eq. 1); each axis moves
+ *    by sqrt(2 D dt) times a standard normal draw (Eqs. 3 and 5).
+ *  - Update order: every alive carrier is moved from the same snapshot of
+ *    the step-start positions (the field loop of Algorithm 1 runs before the
+ *    per-carrier update loop).
+ *  - Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11),
+ *    key = (seed low 32 bits, seed high 32 bits), counter =
+ *    (carrier id, step, event id, domain); domain 0 = diffusion at a step,
+ *    domain 1 = initial cloud.  Uniforms (w + 0.5) 2^-32, Box-Muller
+ *    normals: n0, n1 from (u0, u1), n2 from (u2, u3).
+ *  - Pixel integration: a grid_n x grid_n array of square pixels of side
+ *    pitch centred on (0, 0); bin index floor((x + grid_n pitch / 2) / pitch)
+ *    per axis; carriers outside the grid go to one overflow bin.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---------------------------------------------------------------- types */
+
+typedef struct {
+    double thickness_um, v_bias, v_dep, temperature_k;
+    double pitch_um;
+    int32_t grid_n;
+    double dt_ns, softening_um, eps_r, pair_energy_ev;
+    int32_t mobility; /* 0 = Caughey-Thomas with Jacoboni-Canali hole laws, 1 = constant mu0 */
+    double mu0_override, ec_override, beta_override; /* NaN = model value at T */
+    uint32_t physics; /* bit 0 repulsion, bit 1 drift, bit 2 diffusion */
+    uint64_t seed;
+    int64_t max_steps;
+} oc_params;
+
+typedef struct {
+    double energy_kev;
+    int32_t n_carriers; /* <= 0: round(1000 E / w) */
+    int32_t n_deposits; /* 0: explicit positions */
+    double sigma_um;    /* < 0: Eq. 2 */
+    const double *deposits; /* [n_deposits][3] */
+    const double *xyz;      /* [n_carriers][3] when n_deposits == 0 */
+    const int32_t *ids;     /* optional carrier ids for the RNG counter (default i) */
+    int64_t start_step;
+} oc_event;
+
+enum { OC_OK = 0, OC_EINVAL = -1, OC_EMAXSTEPS = -5, OC_ENONFINITE = -6 };
+enum { OC_REPULSION = 1u, OC_DRIFT = 2u, OC_DIFFUSION = 4u };
+
+/* SI exact values (e, k) and CODATA 2022 vacuum permittivity */
+static const double E_CHARGE = 1.602176634e-19; /* C */
+static const double K_BOLTZ = 1.380649e-23;     /* J/K */
+static const double EPS0 = 8.8541878188e-12;    /* F/m */
+static const double PI = 3.14159265358979323846;
+
+/* --------------------------------------------------------------- Philox */
+
+/* One Philox4x32 round: two 32x32->64 multiplications whose high halves are
+ * mixed with the other two words and the round key (SC'11, Sec. 4.2). */
+static void philox_round(uint32_t c[4], const uint32_t k[2])
+{
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k[0];
+    const uint32_t n2 = hi0 ^ c[3] ^ k[1];
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+}
+
+void oc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k[2] = {key[0], key[1]};
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { /* Weyl key schedule: golden ratio and sqrt(3)-1 */
+            k[0] += 0x9E3779B9u;
+            k[1] += 0xBB67AE85u;
+        }
+        philox_round(c, k);
+    }
+    memcpy(out, c, sizeof c);
+}
+
+static double to_unit(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
+
+/* Three independent standard normals from one Philox block (Box-Muller). */
+void oc_normals3(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, double n[3])
+{
+    const uint32_t ctr[4] = {c0, c1, c2, c3};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    oc_philox4x32_10(ctr, key, w);
+    const double u0 = to_unit(w[0]), u1 = to_unit(w[1]);
+    const double u2 = to_unit(w[2]), u3 = to_unit(w[3]);
+    const double ra = sqrt(-2.0 * log(u0));
+    const double rb = sqrt(-2.0 * log(u2));
+    n[0] = ra * cos(2.0 * PI * u1);
+    n[1] = ra * sin(2.0 * PI * u1);
+    n[2] = rb * cos(2.0 * PI * u3);
+}
+
+/* ------------------------------------------------------------- physics */
+
+/* e / (4 pi eps0 eps_r) in V um: field of one elementary charge is K / r^2. */
+double oc_coulomb_k(const oc_params *p) { return E_CHARGE / (4.0 * PI * EPS0 * p->eps_r) * 1e6; }
+
+/* k T / e in volts. */
+double oc_thermal_voltage(const oc_params *p) { return K_BOLTZ * p->temperature_k / E_CHARGE; }
+
+/* Mobility-model parameters at temperature T: mu0 [um^2/(V ns)], Ec [V/um],
+ * beta.  Jacoboni-Canali hole laws: vm = 1.62e8 T^-0.52 cm/s,
+ * Ec = 1.24 T^1.68 V/cm, beta = 0.46 T^0.17, and mu0 = vm / Ec. */
+void oc_mobility_params(const oc_params *p, double out[3])
+{
+    const double T = p->temperature_k;
+    const double vm = 1.62e8 * pow(T, -0.52) * 1e-5; /* cm/s -> um/ns */
+    double ec = 1.24 * pow(T, 1.68) * 1e-4;          /* V/cm -> V/um */
+    double beta = 0.46 * pow(T, 0.17);
+    double mu0 = vm / ec;
+    if (!isnan(p->mu0_override)) mu0 = p->mu0_override;
+    if (!isnan(p->ec_override)) ec = p->ec_override;
+    if (!isnan(p->beta_override)) beta = p->beta_override;
+    out[0] = mu0;
+    out[1] = ec;
+    out[2] = beta;
+}
+
+double oc_mobility(const oc_params *p, double e_mag)
+{
+    double m[3];
+    oc_mobility_params(p, m);
+    if (p->mobility == 1) return m[0];
+    return m[0] / pow(1.0 + pow(e_mag / m[1], m[2]), 1.0 / m[2]);
+}
+
+/* Eq. 6 along the z axis used here (negative: towards the pixel plane). */
+double oc_drift_field(const oc_params *p, double z)
+{
+    if (!(p->physics & OC_DRIFT)) return 0.0;
+    const double H = p->thickness_um;
+    return -((p->v_bias + p->v_dep) / H - 2.0 * p->v_dep * z / (H * H));
+}
+
+/* Eq. 4 field on carrier a from the n carriers in (x, y, z), skipping a. */
+static void repulsion_one(const oc_params *p, int64_t n, const double *x, const double *y,
+                          const double *z, int64_t a, double K, double E[3])
+{
+    const double s2 = p->softening_um * p->softening_um;
+    double ex = 0.0, ey = 0.0, ez = 0.0;
+    for (int64_t b = 0; b < n; ++b) {
+        if (b == a) continue;
+        const double dx = x[a] - x[b], dy = y[a] - y[b], dz = z[a] - z[b];
+        const double r2 = dx * dx + dy * dy + dz * dz + s2;
+        const double inv_r3 = 1.0 / (r2 * sqrt(r2));
+        ex += dx * inv_r3;
+        ey += dy * inv_r3;
+        ez += dz * inv_r3;
+    }
+    E[0] = K * ex;
+    E[1] = K * ey;
+    E[2] = K * ez;
+}
+
+/* Repulsion field of n carriers on each other ([n][3] in, [n][3] out). */
+void oc_field(const oc_params *p, int64_t n, const double *xyz, double *E)
+{
+    double *x = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *y = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *z = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        x[i] = xyz[3 * i];
+        y[i] = xyz[3 * i + 1];
+        z[i] = xyz[3 * i + 2];
+    }
+    const double K = oc_coulomb_k(p);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) repulsion_one(p, n, x, y, z, i, K, E + 3 * i);
+    free(x);
+    free(y);
+    free(z);
+}
+
+/* Algorithm 1, initialisation: N = round(E / w) carriers. */
+int32_t oc_carrier_count(const oc_params *p, const oc_event *ev)
+{
+    if (ev->n_carriers > 0) return ev->n_carriers;
+    return (int32_t)floor(1000.0 * ev->energy_kev / p->pair_energy_ev + 0.5);
+}
+
+/* Eq. 2: sigma = 0.0044 E^1.75 (um, E in keV) unless the event states one. */
+double oc_initial_sigma(const oc_event *ev)
+{
+    if (ev->sigma_um >= 0.0) return ev->sigma_um;
+    return 0.0044 * pow(ev->energy_kev, 1.75);
+}
+
+int32_t oc_pixel_bin(const oc_params *p, double x, double y)
+{
+    const int32_t G = p->grid_n;
+    const double half = 0.5 * G * p->pitch_um;
+    const double fx = floor((x + half) / p->pitch_um);
+    const double fy = floor((y + half) / p->pitch_um);
+    if (fx >= 0.0 && fx < G && fy >= 0.0 && fy < G) return (int32_t)fy * G + (int32_t)fx;
+    return G * G;
+}
+
+static int check_params(const oc_params *p)
+{
+    if (!(p->thickness_um > 0.0) || !(p->dt_ns > 0.0) || !(p->temperature_k > 0.0)) return OC_EINVAL;
+    if (!(p->pitch_um > 0.0) || p->grid_n < 1 || !(p->softening_um >= 0.0) || !(p->eps_r > 0.0))
+        return OC_EINVAL;
+    if (!(p->pair_energy_ev > 0.0) || p->mobility < 0 || p->mobility > 1) return OC_EINVAL;
+    if ((p->physics & OC_DRIFT) && !(p->v_bias > p->v_dep && p->v_dep >= 0.0)) return OC_EINVAL;
+    double m[3];
+    oc_mobility_params(p, m);
+    if (!(m[0] > 0.0) || !(m[1] > 0.0) || !(m[2] > 0.0)) return OC_EINVAL;
+    return OC_OK;
+}
+
+typedef struct {
+    int32_t n;
+    double *x, *y, *z;
+    double *nx, *ny, *nz;
+    int32_t *id;
+    unsigned char *alive;
+    int64_t *act; /* indices of the alive carriers, in carrier order */
+    double *ax, *ay, *az;
+} oc_work;
+
+static void retire(const oc_params *p, oc_work *w, int32_t i, int64_t step, int32_t *pix,
+                   double *xyz_out, int32_t *cstep)
+{
+    w->alive[i] = 0;
+    xyz_out[3 * i] = w->x[i];
+    xyz_out[3 * i + 1] = w->y[i];
+    xyz_out[3 * i + 2] = w->z[i];
+    cstep[i] = (int32_t)step;
+    pix[oc_pixel_bin(p, w->x[i], w->y[i])] += 1;
+}
+
+/* Simulate one event to completion (or max_steps).  Outputs are indexed by
+ * the carrier's position in the event. */
+static int run_event(const oc_params *p, const oc_event *ev, uint64_t eid, int parallel_targets,
+                     int32_t *pix, double *xyz_out, int32_t *cstep, int64_t *steps_out,
+                     uint64_t *pairs_out)
+{
+    const int32_t n = oc_carrier_count(p, ev);
+    const double H = p->thickness_um;
+    const double sigma = oc_initial_sigma(ev);
+    const double K = oc_coulomb_k(p);
+    const double kT = oc_thermal_voltage(p);
+    const double dt = p->dt_ns;
+    for (int32_t g = 0; g <= p->grid_n * p->grid_n; ++g) pix[g] = 0;
+    *steps_out = 0;
+    *pairs_out = 0;
+    if (n <= 0) return OC_OK;
+
+    oc_work w;
+    const size_t nd = (size_t)n;
+    w.n = n;
+    w.x = malloc(nd * sizeof(double));
+    w.y = malloc(nd * sizeof(double));
+    w.z = malloc(nd * sizeof(double));
+    w.nx = malloc(nd * sizeof(double));
+    w.ny = malloc(nd * sizeof(double));
+    w.nz = malloc(nd * sizeof(double));
+    w.ax = malloc(nd * sizeof(double));
+    w.ay = malloc(nd * sizeof(double));
+    w.az = malloc(nd * sizeof(double));
+    w.id = malloc(nd * sizeof(int32_t));
+    w.alive = malloc(nd);
+    w.act = malloc(nd * sizeof(int64_t));
+    int status = OC_OK;
+
+    /* initial cloud: Gaussian around each deposit (Algorithm 1, Eq. 2) */
+    for (int32_t i = 0; i < n; ++i) {
+        w.id[i] = ev->ids ? ev->ids[i] : i;
+        cstep[i] = -1;
+        if (ev->n_deposits > 0) {
+            const double *d = ev->deposits + 3 * (i % ev->n_deposits);
+            double g[3];
+            oc_normals3(p->seed, (uint32_t)w.id[i], 0u, (uint32_t)eid, 1u, g);
+            w.x[i] = d[0] + sigma * g[0];
+            w.y[i] = d[1] + sigma * g[1];
+            w.z[i] = d[2] + sigma * g[2];
+        } else {
+            w.x[i] = ev->xyz[3 * i];
+            w.y[i] = ev->xyz[3 * i + 1];
+            w.z[i] = ev->xyz[3 * i + 2];
+            if (!isfinite(w.x[i]) || !isfinite(w.y[i]) || !isfinite(w.z[i])) status = OC_ENONFINITE;
+        }
+        if (w.z[i] > H) w.z[i] = 2.0 * H - w.z[i];
+        w.alive[i] = 1;
+    }
+    if (status != OC_OK) goto done;
+    for (int32_t i = 0; i < n; ++i)
+        if (w.z[i] <= 0.0) retire(p, &w, i, ev->start_step, pix, xyz_out, cstep);
+
+    int64_t step = ev->start_step;
+    for (;;) {
+        /* snapshot of the alive set, in carrier order */
+        int64_t na = 0;
+        for (int32_t i = 0; i < n; ++i)
+            if (w.alive[i]) {
+                w.ax[na] = w.x[i];
+                w.ay[na] = w.y[i];
+                w.az[na] = w.z[i];
+                w.act[na++] = i;
+            }
+        if (na == 0) break;
+        if (step - ev->start_step >= p->max_steps) {
+            status = OC_EMAXSTEPS;
+            break;
+        }
+        *pairs_out += (uint64_t)na * (uint64_t)(na - 1);
+#pragma omp parallel for schedule(static) if (parallel_targets)
+        for (int64_t a = 0; a < na; ++a) {
+            const int64_t i = w.act[a];
+            double Er[3] = {0.0, 0.0, 0.0};
+            if (p->physics & OC_REPULSION) repulsion_one(p, na, w.ax, w.ay, w.az, a, K, Er);
+            const double Ex = Er[0], Ey = Er[1], Ez = Er[2] + oc_drift_field(p, w.az[a]);
+            const double Emag = sqrt(Ex * Ex + Ey * Ey + Ez * Ez);
+            const double mu = oc_mobility(p, Emag);
+            double g[3] = {0.0, 0.0, 0.0};
+            double hop = 0.0;
+            if (p->physics & OC_DIFFUSION) {
+                const double D = mu * kT;
+                hop = sqrt(2.0 * D * dt);
+                oc_normals3(p->seed, (uint32_t)w.id[i], (uint32_t)step, (uint32_t)eid, 0u, g);
+            }
+            w.nx[i] = w.ax[a] + mu * Ex * dt + hop * g[0];
+            w.ny[i] = w.ay[a] + mu * Ey * dt + hop * g[1];
+            w.nz[i] = w.az[a] + mu * Ez * dt + hop * g[2];
+        }
+        step += 1;
+        for (int64_t a = 0; a < na; ++a) {
+            const int64_t i = w.act[a];
+            w.x[i] = w.nx[i];
+            w.y[i] = w.ny[i];
+            w.z[i] = w.nz[i] > H ? 2.0 * H - w.nz[i] : w.nz[i];
+            if (w.z[i] <= 0.0) retire(p, &w, (int32_t)i, step, pix, xyz_out, cstep);
+        }
+    }
+    *steps_out = step - ev->start_step;
+    /* carriers still alive report their current position */
+    for (int32_t i = 0; i < n; ++i)
+        if (w.alive[i]) {
+            xyz_out[3 * i] = w.x[i];
+            xyz_out[3 * i + 1] = w.y[i];
+            xyz_out[3 * i + 2] = w.z[i];
+        }
+done:
+    free(w.x); free(w.y); free(w.z);
+    free(w.nx); free(w.ny); free(w.nz);
+    free(w.ax); free(w.ay); free(w.az);
+    free(w.id); free(w.alive); free(w.act);
+    return status;
+}
+
+/* Run a batch.  Event b uses RNG event id first_event_id + b.  Outputs:
+ * pix [B][grid_n^2 + 1], xyz_out [sum N_e][3], cstep [sum N_e] (-1 = alive),
+ * steps [B], pairs = sum over steps of N_a (N_a - 1).  Returns the worst
+ * status over events. */
+int oc_run(const oc_params *p, const oc_event *ev, int32_t n_events, uint64_t first_event_id,
+           int32_t *pix, double *xyz_out, int32_t *cstep, int64_t *steps, uint64_t *pairs)
+{
+    int st = check_params(p);
+    if (st != OC_OK) return st;
+    if (n_events < 0) return OC_EINVAL;
+    int64_t *off = malloc(sizeof(int64_t) * (size_t)(n_events + 1));
+    off[0] = 0;
+    for (int32_t b = 0; b < n_events; ++b) {
+        if (ev[b].n_deposits < 0 || (ev[b].n_deposits == 0 && ev[b].n_carriers > 0 && !ev[b].xyz) ||
+            (ev[b].n_deposits > 0 && !ev[b].deposits)) {
+            free(off);
+            return OC_EINVAL;
+        }
+        const int32_t n = oc_carrier_count(p, &ev[b]);
+        off[b + 1] = off[b] + (n > 0 ? n : 0);
+    }
+    int nthreads = 1;
+#ifdef _OPENMP
+    nthreads = omp_get_max_threads();
+#endif
+    const int outer = n_events >= 2 * nthreads;
+    const int G1 = p->grid_n * p->grid_n + 1;
+    uint64_t total_pairs = 0;
+    int worst = OC_OK;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : total_pairs) if (outer)
+    for (int32_t b = 0; b < n_events; ++b) {
+        uint64_t pr = 0;
+        const int s = run_event(p, &ev[b], first_event_id + (uint64_t)b, !outer, pix + (size_t)b * G1,
+                                xyz_out + 3 * off[b], cstep + off[b], steps + b, &pr);
+        total_pairs += pr;
+        if (s != OC_OK) {
+#pragma omp critical
+            {
+                if (worst == OC_OK || s < worst) worst = s;
+            }
+        }
+    }
+    if (pairs) *pairs = total_pairs;
+    free(off);
+    return worst;
+}
+
+void oc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int oc_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

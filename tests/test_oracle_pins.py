@@ -1,0 +1,421 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a library
+routine (rocRAND's Philox, scipy's CODATA constants and normal law), a closed
+form of the model (uniform-field drift, Eq. 9 drift time, 2Dt diffusion
+variance, the two-charge and regular-polyhedron expansion laws), an invariant
+(zero net repulsion, conservation of carriers), or an exact convention
+(pixel binning, back-side mirroring).
+"""
+import json
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.constants as sc
+from scipy import stats
+
+from workloads import Batch, Sensor, explicit_batch, single_8kev
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _sensor(**kw):
+    base = dict(thickness_um=320.0, v_bias=150.0, v_dep=60.0, dt_ns=0.05, seed=7)
+    base.update(kw)
+    return Sensor(**base)
+
+
+def _K(eps_r=11.7):
+    # e / (4 pi eps0 eps_r) in V um, from scipy's CODATA values
+    return sc.e / (4 * math.pi * sc.epsilon_0 * eps_r) * 1e6
+
+
+# ------------------------------------------------------------------ RNG
+
+@pytest.fixture(scope="module")
+def rocrand_philox(tmp_path_factory):
+    if shutil.which("g++") is None or not os.path.exists("/opt/rocm/include/rocrand"):
+        pytest.skip("rocRAND headers or g++ not available")
+    exe = str(tmp_path_factory.mktemp("rr") / "philox_rocrand")
+    subprocess.run(["g++", "-O1", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                    os.path.join(HERE, "helpers", "philox_rocrand.cpp"), "-o", exe], check=True)
+
+    def run(rows):
+        inp = "\n".join(" ".join(str(int(v)) for v in r) for r in rows) + "\n"
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+        return np.array([[int(t) for t in line.split()] for line in out.strip().splitlines()],
+                        dtype=np.uint64)
+    return run
+
+
+def test_philox_matches_rocrand(oracle_lib, rocrand_philox):
+    rng = np.random.default_rng(1)
+    rows = [(0, 0, 0, 0, 0, 0), (2**32 - 1, 2**29, 2**32 - 1, 2**32 - 1, 2**32 - 1, 2**32 - 1)]
+    for _ in range(200):
+        rows.append((rng.integers(0, 2**32), rng.integers(0, 2**29), rng.integers(0, 2**32),
+                     rng.integers(0, 2**32), rng.integers(0, 2**32), rng.integers(0, 2**32)))
+    ref = rocrand_philox(rows)
+    got = np.array([oracle_lib.philox(r[:4], r[4:]) for r in rows], dtype=np.uint64)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_normals_are_standard_and_independent(oracle_lib):
+    n = 20000
+    a = np.array([oracle_lib.normals3(3, i, 5, 11, 0) for i in range(n)])
+    b = np.array([oracle_lib.normals3(3, i, 5, 11, 1) for i in range(n)])  # other domain
+    for col in range(3):
+        x = a[:, col]
+        assert abs(x.mean()) < 5 / math.sqrt(n)
+        assert abs(x.var() - 1.0) < 5 * math.sqrt(2.0 / n)
+        assert stats.kstest(x, "norm").pvalue > 1e-4
+    c = np.corrcoef(np.column_stack([a, b]).T)
+    off = c[~np.eye(6, dtype=bool)]
+    assert np.abs(off).max() < 5 / math.sqrt(n)
+
+
+# ------------------------------------------------------------ constants
+
+def test_coulomb_and_thermal_constants(oracle_lib):
+    s = _sensor()
+    assert oracle_lib.coulomb_k(s) == pytest.approx(_K(11.7), rel=1e-12, abs=0)
+    assert oracle_lib.coulomb_k(s.replace(eps_r=1.0)) == pytest.approx(_K(1.0), rel=1e-12, abs=0)
+    for T in (250.0, 293.0, 307.85):
+        assert oracle_lib.thermal_voltage(s.replace(temperature_k=T)) == \
+            pytest.approx(sc.k * T / sc.e, rel=1e-12, abs=0)
+
+
+def test_golden_initialisation(oracle_lib):
+    """Algorithm 1 initialisation: N = round(E / w) and Eq. 2 initial width."""
+    with open(os.path.join(HERE, "golden", "alg1_init.json")) as f:
+        g = json.load(f)
+    for case in g["carrier_count"]:
+        s = _sensor(pair_energy_ev=case["w_ev"])
+        b = Batch([case["E_kev"]], [0], [1.0], [1], [[0, 0, 10]])
+        assert oracle_lib.carrier_counts(s, b)[0] == case["N"], case
+    for case in g["initial_sigma"]:
+        b = Batch([case["E_kev"]], [10], [-1.0], [1], [[0, 0, 10]])
+        assert oracle_lib.initial_sigma(b) == pytest.approx(case["sigma_um"], rel=2e-4), case
+
+
+# ------------------------------------------------------------- mobility
+
+def test_mobility_limits_and_hole_values(oracle_lib):
+    s = _sensor(temperature_k=300.0)
+    mu0, ec, beta = oracle_lib.mobility_params(s)
+    # low-field limit and saturation velocity of the Caughey-Thomas form
+    assert oracle_lib.mobility(s, 1e-9) == pytest.approx(mu0, rel=1e-9)
+    v_hi = oracle_lib.mobility(s, 1e5 * ec) * 1e5 * ec
+    assert v_hi == pytest.approx(mu0 * ec, rel=1e-3)
+    assert oracle_lib.mobility(s, ec) == pytest.approx(mu0 / 2 ** (1 / beta), rel=1e-12)
+    # velocity rises, mobility falls with field
+    E = np.linspace(0.01, 20, 200)
+    mu = np.array([oracle_lib.mobility(s, e) for e in E])
+    assert np.all(np.diff(mu) < 0) and np.all(np.diff(mu * E) > 0)
+    # silicon holes at 300 K: low-field mobility ~ 450-480 cm^2/Vs,
+    # saturation velocity ~ 8.4e6 cm/s (um^2/(V ns) = 10 cm^2/Vs; um/ns = 1e5 cm/s)
+    assert 420 < mu0 * 10 < 520
+    assert mu0 * ec * 1e5 == pytest.approx(8.4e6, rel=0.02)
+    # constant model and overrides
+    sc_ = s.replace(mobility="constant", mu0_override=40.0)
+    assert oracle_lib.mobility(sc_, 3.0) == 40.0
+    s1 = s.replace(beta_override=1.0, mu0_override=45.0, ec_override=2.0)
+    assert oracle_lib.mobility(s1, 2.0) == pytest.approx(22.5, rel=1e-14)
+
+
+# ---------------------------------------------------------- drift field
+
+def test_drift_field_integrates_to_bias(oracle_lib):
+    for H, vb, vd in [(320.0, 150.0, 60.0), (450.0, 200.0, 90.0), (320.0, 150.0, 0.0)]:
+        s = _sensor(thickness_um=H, v_bias=vb, v_dep=vd)
+        z = np.linspace(0, H, 2001)
+        E = np.array([oracle_lib.drift_field(s, t) for t in z])
+        # potential drop across the sensor equals the bias; field points to the pixels
+        assert np.trapezoid(E, z) == pytest.approx(-vb, rel=1e-12)
+        assert E[0] == pytest.approx(-(vb + vd) / H) and E[-1] == pytest.approx(-(vb - vd) / H)
+        assert np.allclose(np.diff(E, 2), 0, atol=1e-12)  # linear (uniform doping)
+    assert oracle_lib.drift_field(_sensor(drift=False), 10.0) == 0.0
+
+
+# ------------------------------------------------------- closed forms
+
+def test_uniform_field_drift(oracle_lib):
+    """P1: constant mobility, Vd = 0: z_n = z0 - n mu0 (Vb/H) dt."""
+    mu0 = 45.0
+    s = _sensor(v_dep=0.0, repulsion=False, diffusion=False, mobility="constant", mu0_override=mu0)
+    v = mu0 * s.v_bias / s.thickness_um
+    z0 = np.array([50.3, 123.456, 7.77, 319.0])
+    xyz = np.column_stack([np.linspace(-3, 3, 4), np.linspace(1, 2, 4), z0])
+    r = oracle_lib.run(s, explicit_batch([xyz]))
+    assert r["status"] == 0
+    n = np.ceil(z0 / (v * s.dt_ns)).astype(int)
+    np.testing.assert_array_equal(r["cstep"], n)
+    np.testing.assert_allclose(r["xyz"][:, :2], xyz[:, :2], rtol=0, atol=0)
+    np.testing.assert_allclose(r["xyz"][:, 2], z0 - n * v * s.dt_ns, atol=1e-9)
+    # Jacoboni-Canali mobility at |E| = Vb/H gives the same law with mu(E)
+    sj = s.replace(mobility="jacoboni", mu0_override=math.nan)
+    vj = oracle_lib.mobility(sj, s.v_bias / s.thickness_um) * s.v_bias / s.thickness_um
+    rj = oracle_lib.run(sj, explicit_batch([xyz]))
+    np.testing.assert_array_equal(rj["cstep"], np.ceil(z0 / (vj * s.dt_ns)).astype(int))
+
+
+def test_linear_field_drift_time_eq9(oracle_lib):
+    """P2: beta = 1 mobility in the linear field; Eq. 9 is the exact drift time.
+
+    With E(z) = E0 - k z (here E0 = (Vb+Vd)/H at the pixel plane and
+    k = 2 Vd / H^2), t = (1/mu0) [ln(E(0)/E(z0)) / k + z0 / Ec].
+    """
+    mu0, ec = 48.0, 1.7
+    errs = []
+    for dt in (0.05, 0.025, 0.0125):
+        s = _sensor(dt_ns=dt, repulsion=False, diffusion=False, beta_override=1.0,
+                    mu0_override=mu0, ec_override=ec)
+        H, vb, vd = s.thickness_um, s.v_bias, s.v_dep
+        k = 2 * vd / H**2
+        E = lambda z: (vb + vd) / H - k * z
+        z0 = np.array([10.0, 80.0, 150.0, 250.0, 319.0])
+        t_exact = (np.log(E(0) / E(z0)) / k + z0 / ec) / mu0
+        r = oracle_lib.run(s, explicit_batch([np.column_stack([np.zeros(5), np.zeros(5), z0])]))
+        t_mc = r["cstep"] * dt
+        err = np.abs(t_mc - t_exact)
+        assert np.all(err < 2 * dt), (dt, err)
+        errs.append(err.max())
+    # first-order convergence in dt
+    assert errs[2] < 0.6 * errs[0]
+
+
+def test_diffusion_variance(oracle_lib):
+    """P3: no repulsion, sigma0 = 0, uniform field: var = 2 D t per axis, D = mu kT/e."""
+    mu0, n, steps = 45.0, 20000, 20
+    s = _sensor(v_dep=0.0, repulsion=False, mobility="constant", mu0_override=mu0,
+                max_steps=steps, temperature_k=293.0)
+    z0 = 300.0
+    xyz = np.tile([[1.0, -2.0, z0]], (n, 1))
+    r = oracle_lib.run(s, explicit_batch([xyz]))
+    assert r["status"] == -5  # stopped by max_steps with every carrier alive
+    assert np.all(r["cstep"] == -1)
+    t = steps * s.dt_ns
+    D = mu0 * sc.k * s.temperature_k / sc.e
+    var = 2 * D * t
+    se = var * math.sqrt(2.0 / n)
+    p = r["xyz"]
+    assert abs(p[:, 0].var() - var) < 5 * se
+    assert abs(p[:, 1].var() - var) < 5 * se
+    assert abs(p[:, 2].var() - var) < 5 * se
+    v = mu0 * s.v_bias / s.thickness_um
+    assert abs(p[:, 2].mean() - (z0 - v * t)) < 5 * math.sqrt(var / n)
+    assert abs(p[:, 0].mean() - 1.0) < 5 * math.sqrt(var / n)
+
+
+def _two_charge(oracle_lib, soft, dt, steps, r0=1.0, mu0=48.0):
+    s = _sensor(repulsion=True, drift=False, diffusion=False, mobility="constant",
+                mu0_override=mu0, softening_um=soft, dt_ns=dt, max_steps=steps)
+    xyz = np.array([[-r0 / 2, 0.0, 100.0], [r0 / 2, 0.0, 100.0]])
+    r = oracle_lib.run(s, explicit_batch([xyz]))
+    assert r["status"] == -5
+    p = r["xyz"]
+    return p[1, 0] - p[0, 0], s, p
+
+
+def test_two_charge_separation(oracle_lib):
+    """P4: dr/dt = 2 mu0 K r / (r^2 + s^2)^(3/2); s = 0 gives r^3 = r0^3 + 6 mu0 K t."""
+    mu0, r0 = 48.0, 1.0
+    K = _K()
+    errs = []
+    for dt, steps in ((0.02, 500), (0.01, 1000)):
+        r, s, p = _two_charge(oracle_lib, 0.0, dt, steps, r0, mu0)
+        t = dt * steps
+        exact = (r0**3 + 6 * mu0 * K * t) ** (1 / 3)
+        errs.append(abs(r - exact) / exact)
+        assert errs[-1] < 1e-4
+        assert np.all(p[:, 1:] == [[0.0, 100.0], [0.0, 100.0]])
+        assert p[0, 0] == -p[1, 0]  # symmetric expansion about the centre
+    assert errs[1] < 0.6 * errs[0]  # first-order (explicit Euler) convergence
+    # softened law: G(w) - G(w0) = 2 mu0 K t with w = sqrt(r^2 + s^2)
+    soft = 0.3
+    G = lambda r: (lambda w: w**3 / 3 + soft**2 * w + soft**3 / 2 * math.log((w - soft) / (w + soft)))(
+        math.sqrt(r * r + soft * soft))
+    r, s, _ = _two_charge(oracle_lib, soft, 0.005, 2000, r0, mu0)
+    t = 0.005 * 2000
+    from scipy.optimize import brentq
+    exact = brentq(lambda x: G(x) - G(r0) - 2 * mu0 * K * t, r0, 10.0, xtol=1e-14)
+    assert abs(r - exact) / exact < 1e-4
+
+
+def _polyhedra():
+    tri = np.array([[math.cos(a), math.sin(a), 0.0] for a in (0, 2 * math.pi / 3, 4 * math.pi / 3)])
+    tet = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]]) / math.sqrt(3)
+    octa = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], float)
+    cube = np.array([[a, b, c] for a in (-1, 1) for b in (-1, 1) for c in (-1, 1)]) / math.sqrt(3)
+    return {"triangle": tri, "tetrahedron": tet, "octahedron": octa, "cube": cube}
+
+
+def test_regular_polyhedra_expand_self_similarly(oracle_lib):
+    """P5: vertices of a regular polyhedron stay on it; R^3 = R0^3 + 3 mu0 K C t.
+
+    For unit circumradius the radial field sum is C = (1/2) sum_j 1/d_ij over
+    the chord lengths d_ij from one vertex (each term (1 - cos t)/d^3 = 1/(2d)).
+    The Jacobi (snapshot) update keeps the symmetry exactly; a sequential
+    update would not.
+    """
+    mu0, dt, steps, R0 = 48.0, 0.01, 1000, 1.0
+    K = _K()
+    centre = np.array([0.0, 0.0, 100.0])
+    for name, V in _polyhedra().items():
+        d = np.linalg.norm(V[0] - V[1:], axis=1)
+        C = 0.5 * np.sum(1.0 / d)
+        s = _sensor(drift=False, diffusion=False, mobility="constant", mu0_override=mu0,
+                    softening_um=0.0, dt_ns=dt, max_steps=steps)
+        # field at t = 0 is radial with magnitude K C / R0^2
+        E0 = oracle_lib.field(s, V * R0 + centre)
+        np.testing.assert_allclose(E0, K * C * V / R0**2, rtol=0, atol=1e-13 * K * C)
+        r = oracle_lib.run(s, explicit_batch([V * R0 + centre]))
+        rel = r["xyz"] - centre
+        R = np.linalg.norm(rel, axis=1)
+        exact = (R0**3 + 3 * mu0 * K * C * dt * steps) ** (1 / 3)
+        assert np.all(np.abs(R - exact) / exact < 1e-4), (name, R, exact)
+        assert np.ptp(R) < 1e-12 * exact, name  # shape preserved
+        np.testing.assert_allclose(rel / R[:, None], V, atol=1e-12)
+
+
+# ---------------------------------------------------------- invariants
+
+def test_zero_net_repulsion_and_fixed_centroid(oracle_lib):
+    """P6: pairwise antisymmetry of Eq. 4 -> sum of fields is zero; with a
+    constant mobility and no drift or diffusion the centroid does not move."""
+    rng = np.random.default_rng(5)
+    xyz = rng.normal(size=(700, 3)) * [1.0, 2.0, 0.5] + [3.0, -4.0, 150.0]
+    for soft in (0.0, 0.01, 0.2):
+        s = _sensor(softening_um=soft)
+        E = oracle_lib.field(s, xyz)
+        assert np.abs(E.sum(axis=0)).max() <= 1e-13 * np.abs(E).sum()
+    s = _sensor(drift=False, diffusion=False, mobility="constant", mu0_override=40.0, max_steps=15)
+    r = oracle_lib.run(s, explicit_batch([xyz]))
+    np.testing.assert_allclose(r["xyz"].mean(axis=0), xyz.mean(axis=0), rtol=0, atol=1e-12)
+    assert r["xyz"].std(axis=0).min() > xyz.std(axis=0).min()  # the cloud expanded
+
+
+def test_field_of_point_charge_far_away(oracle_lib):
+    """A tight cluster of n holes acts at distance r like a charge n e: E = n K / r^2."""
+    rng = np.random.default_rng(9)
+    n, dist = 50, 400.0
+    cl = rng.normal(size=(n, 3)) * 0.01 + [0, 0, 100.0]
+    probe = np.array([[dist, 0, 100.0]])
+    E = oracle_lib.field(_sensor(softening_um=0.0), np.vstack([cl, probe]))[-1]
+    d = probe[0] - cl.mean(axis=0)  # monopole about the centroid: no dipole term
+    want = n * _K() * d / np.linalg.norm(d) ** 3
+    np.testing.assert_allclose(E, want, rtol=0, atol=1e-8 * np.linalg.norm(want))
+
+
+def test_conservation_and_completion(oracle_lib):
+    """P11: every carrier retires exactly once and is counted in one bin."""
+    s, b = single_8kev(seed=3)
+    b = Batch(b.energy_kev, [400], [1.5], b.n_deposits, b.deposits, name="small")
+    r = oracle_lib.run(s, b)
+    assert r["status"] == 0
+    assert r["pix"].sum() == 400
+    assert np.all(r["cstep"] >= 1) and r["cstep"].max() == r["steps"][0]
+    assert np.all(r["xyz"][:, 2] <= 0.0)
+    bins = [oracle_lib.pixel_bin(s, x, y) for x, y in r["xyz"][:, :2]]
+    np.testing.assert_array_equal(np.bincount(bins, minlength=26), r["pix"][0])
+
+
+def test_events_are_independent(oracle_lib):
+    """An event simulated alone equals the same event inside a batch (same id)."""
+    rng = np.random.default_rng(2)
+    evs = [rng.normal(size=(n, 3)) + [0, 0, z] for n, z in ((60, 30.0), (90, 80.0), (45, 12.0))]
+    s = _sensor()
+    rb = oracle_lib.run(s, explicit_batch(evs, first_event_id=10))
+    off = rb["offsets"]
+    for b, x in enumerate(evs):
+        ra = oracle_lib.run(s, explicit_batch([x], first_event_id=10 + b))
+        np.testing.assert_array_equal(ra["xyz"], rb["xyz"][off[b]:off[b + 1]])
+        np.testing.assert_array_equal(ra["cstep"], rb["cstep"][off[b]:off[b + 1]])
+        np.testing.assert_array_equal(ra["pix"][0], rb["pix"][b])
+
+
+# ------------------------------------------------------- conventions
+
+def test_pixel_binning_convention(oracle_lib):
+    s = _sensor()
+    cases = {(0.0, 0.0): 12, (12.5, 0.0): 13, (-12.5, 0.0): 12, (12.4999999, 0.0): 12,
+             (-62.5, -62.5): 0, (62.4999, 62.4999): 24, (62.5, 0.0): 25, (0.0, -62.5001): 25,
+             (37.5, 37.5): 24, (-37.5, 12.5): 16}
+    for (x, y), want in cases.items():
+        assert oracle_lib.pixel_bin(s, x, y) == want, (x, y)
+    # carriers placed on or below the pixel plane are collected at step 0
+    xyz = np.array([[x, y, -0.5] for (x, y) in cases] + [[1.0, 1.0, 0.0]])
+    r = oracle_lib.run(s, explicit_batch([xyz]))
+    assert np.all(r["cstep"] == 0) and r["steps"][0] == 0
+    want = np.bincount(list(cases.values()) + [12], minlength=26)
+    np.testing.assert_array_equal(r["pix"][0], want)
+
+
+def test_seeding_cloud_and_back_side_mirror(oracle_lib):
+    s = _sensor(max_steps=0)
+    H = s.thickness_um
+    n, sig = 20000, 2.0
+    b = Batch([8.0], [n], [sig], [1], [[1.0, -1.0, 200.0]])
+    r = oracle_lib.run(s, b)
+    p = r["xyz"]
+    se = sig / math.sqrt(n)
+    assert np.all(np.abs(p.mean(axis=0) - [1.0, -1.0, 200.0]) < 5 * se)
+    assert np.all(np.abs(p.var(axis=0) - sig**2) < 5 * sig**2 * math.sqrt(2.0 / n))
+    # a cloud centred on the entrance side folds into a half-normal below H
+    b2 = Batch([8.0], [n], [sig], [1], [[0.0, 0.0, H]])
+    z = oracle_lib.run(s, b2)["xyz"][:, 2]
+    assert np.all(z <= H)
+    assert abs(np.mean(H - z) - sig * math.sqrt(2 / math.pi)) < 5 * sig / math.sqrt(n)
+    # explicit positions above H are mirrored, z <= 0 is collected at once
+    xyz = np.array([[0, 0, H + 3.0], [0, 0, H - 3.0], [0, 0, -1.0]])
+    r3 = oracle_lib.run(s, explicit_batch([xyz]))
+    np.testing.assert_array_equal(r3["xyz"][:2, 2], [H - 3.0, H - 3.0])
+    np.testing.assert_array_equal(r3["cstep"], [-1, -1, 0])
+    # several deposits: carrier i sits on deposit i mod n_dep (sigma 0)
+    dep = np.array([[0, 0, 10.0], [5, 5, 20.0], [-5, 2, 30.0]])
+    r4 = oracle_lib.run(s, Batch([8.0], [7], [0.0], [3], dep))
+    np.testing.assert_array_equal(r4["xyz"], dep[np.arange(7) % 3])
+
+
+def test_bad_params_rejected(oracle_lib):
+    xyz = np.array([[0, 0, 10.0]])
+    assert oracle_lib.run(_sensor(v_bias=50.0, v_dep=60.0), explicit_batch([xyz]))["status"] == -1
+    assert oracle_lib.run(_sensor(dt_ns=0.0), explicit_batch([xyz]))["status"] == -1
+    assert oracle_lib.run(_sensor(), explicit_batch([[[0, math.nan, 3.0]]]))["status"] == -6
+    # under-depleted is fine when the drift field is off
+    assert oracle_lib.run(_sensor(v_bias=50.0, v_dep=60.0, drift=False, max_steps=2),
+                          explicit_batch([xyz]))["status"] == -5
+
+
+# --------------------------------------------- statistical pixel sharing
+
+def test_pixel_sharing_without_repulsion(oracle_lib):
+    """P10: point source, no repulsion: the share beyond a pixel edge follows
+    the normal law with variance 2 D t (t = collection time)."""
+    mu0, n = 45.0, 20000
+    s = _sensor(v_dep=0.0, repulsion=False, mobility="constant", mu0_override=mu0)
+    x0, z0 = 10.0, 60.0
+    r = oracle_lib.run(s, explicit_batch([np.tile([[x0, 0.0, z0]], (n, 1))]))
+    assert r["status"] == 0
+    t = r["cstep"].mean() * s.dt_ns
+    D = mu0 * sc.k * s.temperature_k / sc.e
+    p_right = 1.0 - stats.norm.cdf((12.5 - x0) / math.sqrt(2 * D * t))
+    got = r["pix"][0][13] / n
+    assert abs(got - p_right) < 5 * math.sqrt(p_right * (1 - p_right) / n) + 0.003
+
+
+def test_oracle_regression_record(oracle_lib):
+    """The committed record (tests/golden/make_golden.py) still reproduces."""
+    with open(os.path.join(HERE, "golden", "oracle_single_8kev.json")) as f:
+        g = json.load(f)
+    s, b = single_8kev(seed=0)
+    r = oracle_lib.run(s, b)
+    assert r["status"] == g["status"] and int(r["steps"][0]) == g["steps"]
+    assert r["pairs"] == g["pairs"]
+    np.testing.assert_array_equal(r["pix"][0], g["pix"])
+    np.testing.assert_array_equal(np.bincount(r["cstep"]), g["cstep_hist"])
+    np.testing.assert_allclose(r["xyz"][:8], g["end_first"], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(r["xyz"].mean(axis=0), g["end_mean"], rtol=0, atol=1e-9)

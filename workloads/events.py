@@ -1,0 +1,287 @@
+"""Seeded synthetic workloads: sensor settings and per-event deposits.
+
+Coordinates are in micrometres with z measured from the pixel (collecting)
+plane, so holes drift towards z = 0 and the back (entrance) side is z = H.
+The paper measures depth from the entrance side (the limits of its drift-time
+integral, Eq. 9, run from the absorption depth h to the thickness H); an
+absorption depth h therefore maps to z0 = H - h here.
+
+Nothing in this module evaluates the transport model. It only draws
+event-level quantities with numpy's PCG64 generator:
+
+* absorption depth h from an exponential law truncated to the sensor
+  (inverse CDF on [0, H)), measured from the entrance side;
+* the entry point (x, y), uniform over the central pixel;
+* the photon energy for mixed batches;
+* for electron tracks, the deposit points along a 3-D random walk.
+
+The carrier count of each event is the one the workload states (E / 3.6 eV
+rounded, e.g. 2222 holes at 8 keV).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclass
+class Sensor:
+    """Planar sensor and run settings (units: um, ns, V, K)."""
+
+    thickness_um: float = 320.0
+    v_bias: float = 150.0
+    v_dep: float = 60.0
+    temperature_k: float = 293.0
+    pitch_um: float = 25.0
+    grid_n: int = 5
+    dt_ns: float = 0.05
+    softening_um: float = 0.01
+    eps_r: float = 11.7
+    pair_energy_ev: float = 3.6
+    mobility: str = "jacoboni"  # "jacoboni" (Caughey-Thomas form) or "constant"
+    mu0_override: float = math.nan  # um^2/(V ns); NaN = model value at T
+    ec_override: float = math.nan  # V/um
+    beta_override: float = math.nan
+    repulsion: bool = True
+    drift: bool = True
+    diffusion: bool = True
+    seed: int = 0
+    max_steps: int = 1_000_000
+
+    def replace(self, **kw) -> "Sensor":
+        return dataclasses.replace(self, **kw)
+
+
+@dataclass
+class Batch:
+    """A batch of events in flat arrays.
+
+    energy_kev[b]   photon / particle energy (used when n_carriers[b] <= 0)
+    n_carriers[b]   carriers of event b; <= 0 means round(1000 E / w)
+    sigma_um[b]     per-axis Gaussian width around each deposit; < 0 means
+                    the energy-dependent initial width of the paper (Eq. 2)
+    n_deposits[b]   >= 1: Gaussian cloud(s) around the deposit points;
+                    0: explicit carrier positions taken from ``xyz``
+    deposits        [sum n_deposits, 3] deposit centres, in event order
+    xyz             [sum of carriers of explicit events, 3], in event order
+    start_step[b]   step index of the given state (0 for a fresh event)
+    first_event_id  event b uses id first_event_id + b in the RNG counter
+    """
+
+    energy_kev: np.ndarray
+    n_carriers: np.ndarray
+    sigma_um: np.ndarray
+    n_deposits: np.ndarray
+    deposits: np.ndarray
+    xyz: Optional[np.ndarray] = None
+    start_step: Optional[np.ndarray] = None
+    first_event_id: int = 0
+    name: str = ""
+
+    def __post_init__(self):
+        self.energy_kev = np.ascontiguousarray(self.energy_kev, dtype=np.float64)
+        B = self.energy_kev.shape[0]
+        self.n_carriers = np.ascontiguousarray(self.n_carriers, dtype=np.int32).reshape(B)
+        self.sigma_um = np.ascontiguousarray(self.sigma_um, dtype=np.float64).reshape(B)
+        self.n_deposits = np.ascontiguousarray(self.n_deposits, dtype=np.int32).reshape(B)
+        self.deposits = np.ascontiguousarray(self.deposits, dtype=np.float64).reshape(-1, 3)
+        if self.xyz is not None:
+            self.xyz = np.ascontiguousarray(self.xyz, dtype=np.float64).reshape(-1, 3)
+        if self.start_step is None:
+            self.start_step = np.zeros(B, dtype=np.int64)
+        self.start_step = np.ascontiguousarray(self.start_step, dtype=np.int64).reshape(B)
+        if int(self.n_deposits.sum()) != self.deposits.shape[0]:
+            raise ValueError("deposits rows must equal sum(n_deposits)")
+
+    @property
+    def n_events(self) -> int:
+        return int(self.energy_kev.shape[0])
+
+    def dep_offsets(self) -> np.ndarray:
+        off = np.zeros(self.n_events + 1, dtype=np.int64)
+        np.cumsum(self.n_deposits, out=off[1:])
+        return off
+
+    def event(self, b: int) -> "Batch":
+        """Event b alone, keeping its RNG id (first_event_id + b)."""
+        return self.subset([b])[0]
+
+    def subset(self, idx: Sequence[int]) -> List["Batch"]:
+        """Single-event batches for the given indices, each keeping its id."""
+        doff = self.dep_offsets()
+        xoff = None
+        if self.xyz is not None:
+            nexp = np.where(self.n_deposits == 0, self.n_carriers, 0).astype(np.int64)
+            xoff = np.zeros(self.n_events + 1, dtype=np.int64)
+            np.cumsum(nexp, out=xoff[1:])
+        out = []
+        for b in idx:
+            b = int(b)
+            xyz = None
+            if xoff is not None and self.n_deposits[b] == 0:
+                xyz = self.xyz[xoff[b]:xoff[b + 1]]
+            out.append(Batch(
+                energy_kev=self.energy_kev[b:b + 1], n_carriers=self.n_carriers[b:b + 1],
+                sigma_um=self.sigma_um[b:b + 1], n_deposits=self.n_deposits[b:b + 1],
+                deposits=self.deposits[doff[b]:doff[b + 1]], xyz=xyz,
+                start_step=self.start_step[b:b + 1],
+                first_event_id=self.first_event_id + b, name=f"{self.name}[{b}]"))
+        return out
+
+    def head(self, n: int) -> "Batch":
+        """The first n events as one batch (ids unchanged)."""
+        n = min(n, self.n_events)
+        doff = self.dep_offsets()
+        xyz = None
+        if self.xyz is not None:
+            nexp = int(np.where(self.n_deposits[:n] == 0, self.n_carriers[:n], 0).sum())
+            xyz = self.xyz[:nexp]
+        return Batch(self.energy_kev[:n], self.n_carriers[:n], self.sigma_um[:n],
+                     self.n_deposits[:n], self.deposits[:doff[n]], xyz,
+                     self.start_step[:n], self.first_event_id, f"{self.name}[:{n}]")
+
+
+# ---------------------------------------------------------------- samplers
+
+def _rng(seed: int, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64([seed, stream]))
+
+
+def trunc_exp_depth(u: np.ndarray, lam_um: np.ndarray, H: float) -> np.ndarray:
+    """Inverse CDF of an exponential absorption law truncated to [0, H)."""
+    return -lam_um * np.log1p(-u * (-np.expm1(-H / lam_um)))
+
+
+def _central_pixel_xy(rng: np.random.Generator, n: int, pitch: float) -> np.ndarray:
+    return rng.uniform(-0.5 * pitch, 0.5 * pitch, size=(n, 2))
+
+
+# carriers stated by the workloads (E / 3.6 eV, rounded)
+_N_AT = {8.0: 2222, 6.0: 1667, 12.0: 3333, 17.5: 4861, 22.0: 6111, 60.0: 16667, 200.0: 55556}
+
+# Attenuation lengths for the mixed-energy batch: a power law through the two
+# end values the workload states (70 um at 6 keV, 1500 um at 22 keV).  A
+# synthetic stand-in, not tabulated silicon data.
+_LAM_LO, _LAM_HI, _E_LO, _E_HI = 70.0, 1500.0, 6.0, 22.0
+
+
+def attenuation_um(e_kev: np.ndarray) -> np.ndarray:
+    p = math.log(_LAM_HI / _LAM_LO) / math.log(_E_HI / _E_LO)
+    return _LAM_LO * (np.asarray(e_kev, dtype=np.float64) / _E_LO) ** p
+
+
+def single_8kev(seed: int = 0) -> tuple[Sensor, Batch]:
+    """One 8 keV photon: 2222 holes, sigma 1 um, 50 um above the pixel plane."""
+    s = Sensor(thickness_um=320.0, v_bias=150.0, v_dep=60.0, dt_ns=0.05, seed=seed)
+    b = Batch(energy_kev=[8.0], n_carriers=[2222], sigma_um=[1.0], n_deposits=[1],
+              deposits=[[0.0, 0.0, 50.0]], name="single_8kev")
+    return s, b
+
+
+def batch_8kev(n_events: int = 256, seed: int = 0) -> tuple[Sensor, Batch]:
+    """8 keV photons, depth ~ truncated Exp(70 um) from the entrance side."""
+    s = Sensor(thickness_um=320.0, v_bias=150.0, v_dep=60.0, dt_ns=0.05, seed=seed)
+    rng = _rng(seed, 1)
+    H = s.thickness_um
+    h = trunc_exp_depth(rng.random(n_events), np.full(n_events, 70.0), H)
+    xy = _central_pixel_xy(rng, n_events, s.pitch_um)
+    dep = np.column_stack([xy, H - h])
+    b = Batch(energy_kev=np.full(n_events, 8.0), n_carriers=np.full(n_events, _N_AT[8.0]),
+              sigma_um=np.full(n_events, 1.0), n_deposits=np.ones(n_events),
+              deposits=dep, name="batch_8kev")
+    return s, b
+
+
+def mixed_energy(n_events: int = 1024, seed: int = 0) -> tuple[Sensor, Batch]:
+    """Energies uniform over {6, 12, 17.5, 22} keV in a 450 um sensor at 200 V."""
+    s = Sensor(thickness_um=450.0, v_bias=200.0, v_dep=90.0, dt_ns=0.05, seed=seed)
+    rng = _rng(seed, 2)
+    H = s.thickness_um
+    levels = np.array([6.0, 12.0, 17.5, 22.0])
+    e = levels[rng.integers(0, 4, size=n_events)]
+    h = trunc_exp_depth(rng.random(n_events), attenuation_um(e), H)
+    xy = _central_pixel_xy(rng, n_events, s.pitch_um)
+    dep = np.column_stack([xy, H - h])
+    n = np.array([_N_AT[float(x)] for x in e])
+    b = Batch(energy_kev=e, n_carriers=n, sigma_um=np.full(n_events, 1.0),
+              n_deposits=np.ones(n_events), deposits=dep, name="mixed_energy")
+    return s, b
+
+
+def gamma_60kev(n_events: int = 64, seed: int = 0) -> tuple[Sensor, Batch]:
+    """60 keV deposits (16,667 holes), depth uniform in a 450 um sensor at 250 V."""
+    s = Sensor(thickness_um=450.0, v_bias=250.0, v_dep=90.0, dt_ns=0.025, seed=seed)
+    rng = _rng(seed, 3)
+    H = s.thickness_um
+    h = rng.uniform(0.0, H, size=n_events)
+    xy = _central_pixel_xy(rng, n_events, s.pitch_um)
+    dep = np.column_stack([xy, H - h])
+    b = Batch(energy_kev=np.full(n_events, 60.0), n_carriers=np.full(n_events, _N_AT[60.0]),
+              sigma_um=np.full(n_events, 1.0), n_deposits=np.ones(n_events),
+              deposits=dep, name="gamma_60kev")
+    return s, b
+
+
+def _fold(z: float, H: float) -> float:
+    while z < 0.0 or z > H:
+        z = -z if z < 0.0 else 2.0 * H - z
+    return z
+
+
+def track_200kev(n_events: int = 16, seed: int = 0, n_segments: int = 40,
+                 seg_len_um: float = 5.0) -> tuple[Sensor, Batch]:
+    """200 keV electron tracks: 40 deposits along a 3-D random walk of 5 um steps.
+
+    The walk starts on the entrance side (z = H) at a point uniform over the
+    central pixel; its first step points into the sensor (-z), later steps
+    are isotropic; positions are folded back into [0, H].  Deposit k is the
+    midpoint of segment k and receives every carrier i with i mod 40 == k.
+    """
+    s = Sensor(thickness_um=320.0, v_bias=150.0, v_dep=60.0, dt_ns=0.05, seed=seed)
+    rng = _rng(seed, 4)
+    H = s.thickness_um
+    deps = []
+    for _ in range(n_events):
+        p = np.array([*rng.uniform(-0.5 * s.pitch_um, 0.5 * s.pitch_um, 2), H])
+        for k in range(n_segments):
+            if k == 0:
+                d = np.array([0.0, 0.0, -1.0])
+            else:
+                v = rng.normal(size=3)
+                d = v / np.linalg.norm(v)
+            q = p + seg_len_um * d
+            mid = 0.5 * (p + q)
+            deps.append([mid[0], mid[1], _fold(mid[2], H)])
+            p = np.array([q[0], q[1], _fold(q[2], H)])
+    b = Batch(energy_kev=np.full(n_events, 200.0), n_carriers=np.full(n_events, _N_AT[200.0]),
+              sigma_um=np.full(n_events, 0.5), n_deposits=np.full(n_events, n_segments),
+              deposits=np.array(deps), name="track_200kev")
+    return s, b
+
+
+def explicit_batch(xyz_per_event: Sequence[np.ndarray], first_event_id: int = 0,
+                   start_step: Optional[Sequence[int]] = None, name: str = "explicit") -> Batch:
+    """Events given by explicit carrier positions ([n_e, 3] each)."""
+    xs = [np.asarray(x, dtype=np.float64).reshape(-1, 3) for x in xyz_per_event]
+    B = len(xs)
+    return Batch(energy_kev=np.zeros(B), n_carriers=[x.shape[0] for x in xs],
+                 sigma_um=np.zeros(B), n_deposits=np.zeros(B), deposits=np.zeros((0, 3)),
+                 xyz=np.concatenate(xs) if xs else np.zeros((0, 3)),
+                 start_step=start_step, first_event_id=first_event_id, name=name)
+
+
+WORKLOADS: Dict[str, Callable[..., tuple]] = {
+    "single_8kev": single_8kev,
+    "batch_8kev": batch_8kev,
+    "mixed_energy": mixed_energy,
+    "gamma_60kev": gamma_60kev,
+    "track_200kev": track_200kev,
+}
+
+
+def make_workload(name: str, **kw) -> tuple[Sensor, Batch]:
+    return WORKLOADS[name](**kw)
