@@ -1,0 +1,160 @@
+"""Throughput of the batched repulsion Monte Carlo on one MI355X.
+
+One bench step = one whole batch simulated to completion through the C ABI:
+seeding of every event's initial cloud on the device, the time-step loop
+(all-pairs repulsion, drift, diffusion, collection, pixel integration,
+compaction) until every hole is collected, and the pixel counts copied back.
+
+Printed as one JSON line: pair-interactions/s of the FP32-batched path
+(value), events/s, the FP64-plain comparison (one event at a time, FP64
+field), the roofline of the repulsion-step kernel (timed with HIP events on
+the library's stream) and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "pair-interactions/s + events/s, FP32-batched vs FP64-plain at ≤1e-3 pixel-fraction err"
+FP32_VECTOR_PEAK = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 64 lanes x 2 x 2 x 2.4 GHz)
+FLOP_PER_PAIR = 20            # N-body convention for one softened pair interaction
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batch_8kev")
+    ap.add_argument("--events", type=int, default=0, help="override the number of events")
+    ap.add_argument("--plain-events", type=int, default=32,
+                    help="events of the FP64-plain comparison (rate extrapolated)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--launch", default="", help="kt,bs,chunk override")
+    return ap.parse_args()
+
+
+def simulate(ct, sim, batch):
+    sim.seed(batch)
+    st, done, act = sim.step(0)
+    if st != 0:
+        raise RuntimeError(f"batch did not finish: status {st}, {act} holes left")
+    return sim.collect()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not "
+                                   "supported (events shard with no per-step exchange)",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_2506_09712_amd as ct
+    from workloads import make_workload
+
+    kw = {"n_events": a.events} if a.events else {}
+    sensor, batch = make_workload(a.workload, **kw)
+    launch = tuple(int(v) for v in a.launch.split(",")) if a.launch else None
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    print(f"bench: {a.workload} {batch.n_events} events, {int(batch.n_carriers.sum())} holes; "
+          f"warmup {a.warmup}, steps {a.steps}", file=sys.stderr, flush=True)
+    sim = ct.Simulator(sensor, ct.CT_FP32, device=0, options=ct.CT_OPT_TIMING, launch=launch)
+    for _ in range(a.warmup):
+        simulate(ct, sim, batch)
+    torch.cuda.synchronize()
+    pairs = 0
+    kern_ms = 0.0
+    launches = 0
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        r = simulate(ct, sim, batch)
+        pairs += r["pairs"]
+        kern_ms += r["stats"].field_kernel_ms
+        launches += r["stats"].field_launches
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = r["stats"]
+    value = pairs / wall
+    events_per_s = batch.n_events * a.steps / wall
+    achieved = FLOP_PER_PAIR * pairs / (kern_ms * 1e-3) if kern_ms > 0 else None
+    print(f"bench: fp32-batched {value:.3e} pairs/s, {events_per_s:.1f} events/s, "
+          f"step kernel {kern_ms / max(launches, 1):.3f} ms avg over {launches} launches",
+          file=sys.stderr, flush=True)
+    sim.close()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "pair-interactions/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * wall / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {batch.n_events} events, "
+                               f"{int(batch.n_carriers.sum())} holes, "
+                               f"{sensor.thickness_um:g} um Si at {sensor.v_bias:g} V, "
+                               f"dt {sensor.dt_ns:g} ns; FP32 field, FP64 state, all events "
+                               f"in one launch per step",
+                   "events": batch.n_events, "holes": int(batch.n_carriers.sum()),
+                   "launch": {"targets_per_thread": st.targets_per_thread,
+                              "block": st.block_size, "chunk_len": st.chunk_len}},
+        "events_per_s": events_per_s,
+        "pairs_per_run": pairs // a.steps,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12 if achieved else None,
+                     "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK if achieved else None, "traffic": None,
+                     "kernel": "k_step_f32", "avg_launch_ms": kern_ms / max(launches, 1),
+                     "flop_per_pair": FLOP_PER_PAIR},
+    }
+
+    if not a.no_plain:
+        # FP64-plain: the same events one at a time with the FP64 field
+        n_plain = min(a.plain_events, batch.n_events)
+        simp = ct.Simulator(sensor, ct.CT_FP64, device=0)
+        ppairs = 0
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for e in range(n_plain):
+            rr = simulate(ct, simp, batch.event(e))
+            ppairs += rr["pairs"]
+        torch.cuda.synchronize()
+        pwall = time.perf_counter() - t1
+        simp.close()
+        prate = ppairs / pwall
+        out["fp64_plain"] = {"value": prate, "unit": "pair-interactions/s",
+                             "events_per_s": n_plain / pwall, "events": n_plain}
+        out["speedup_fp32_batched_vs_fp64_plain"] = value / prate
+        print(f"bench: fp64-plain {prate:.3e} pairs/s over {n_plain} events", file=sys.stderr,
+              flush=True)
+
+    if not a.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        cpairs, t2, k = 0, time.perf_counter(), 0
+        while k < batch.n_events and (time.perf_counter() - t2) < a.cpu_seconds:
+            o = oracle.run(sensor, batch.event(k))
+            cpairs += o["pairs"]
+            k += 1
+        cwall = time.perf_counter() - t2
+        out["cpu_baseline"] = {"value": cpairs / cwall, "unit": "pair-interactions/s",
+                               "cores": oracle.threads(), "kind": "oracle",
+                               "sample": f"events 0..{k - 1} of {a.workload}, each simulated "
+                                         f"to completion alone ({cpairs:.3e} pairs, {cwall:.1f} s)",
+                               "events_per_s": k / cwall}
+        print(f"bench: oracle {cpairs / cwall:.3e} pairs/s on {oracle.threads()} threads",
+              file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

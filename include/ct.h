@@ -1,0 +1,201 @@
+/*
+ * ct.h - C ABI of the MI355X (gfx950) brute-force charge-transport Monte Carlo.
+ *
+ * The library simulates the holes of many independent X-ray / electron events
+ * in a planar p-on-n silicon sensor with the comprehensive time-stepping method
+ * of Xie et al., arXiv:2506.09712, Sec. 2.1 (Eqs. 2-6) and Appendix A
+ * (Algorithm 1).  Each step evaluates, for every alive hole i of an event,
+ *
+ *     E_rep,i = K * sum_{j != i, j alive in the same event}
+ *               (r_i - r_j) / (|r_i - r_j|^2 + s^2)^(3/2),   K = e/(4 pi eps0 eps_r)
+ *
+ * (Eq. 4 for holes, with an optional Plummer softening s), adds the linear
+ * drift field of Eq. 6, evaluates the Caughey-Thomas / Jacoboni-Canali
+ * mobility at |E_drift + E_rep|, and moves the hole by mu E dt plus a
+ * Gaussian diffusion step of variance 2 D dt per axis, D = mu k T / e
+ * (Eqs. 3 and 5).  Holes whose update leaves them at z <= 0 are collected
+ * on the pixel plane and counted in a grid_n x grid_n pixel array.
+ *
+ * Units: micrometre, nanosecond, volt, kelvin.  z is the distance from the
+ * pixel (collecting) plane; the paper's z (from the entrance side) is H - z.
+ *
+ * Conventions shared by every call:
+ *  - Every call returns ct_status; no exception or abort crosses the ABI.
+ *    ct_last_error() returns a thread-local message for the last failure.
+ *  - Host arrays passed in are owned by the caller and only read during the
+ *    call.  Device memory belongs to the context, or to the caller when it
+ *    binds a workspace (ct_bind_workspace); a bound workspace must outlive
+ *    the context.
+ *  - A context is used by one host thread at a time.  Separate contexts are
+ *    independent.  Work is issued on the context's HIP stream; every call
+ *    that returns results synchronises that stream before returning.
+ *  - CT_EINVAL / CT_ESTATE leave the context unchanged.  CT_EDEVICE means a
+ *    HIP call failed; the context must then only be destroyed.
+ *    CT_EMAXSTEPS keeps the state so it can be collected or continued.
+ */
+#ifndef CT_H
+#define CT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CT_ABI_VERSION 1u
+
+typedef struct ct_ctx ct_ctx; /* opaque, owned by the library */
+
+typedef enum {
+    CT_OK = 0,
+    CT_EINVAL = -1,     /* bad argument or parameter */
+    CT_ESTATE = -2,     /* call out of order (e.g. ct_step before ct_seed_events) */
+    CT_ENOMEM = -3,     /* device allocation failed or bound workspace too small */
+    CT_EDEVICE = -4,    /* no gfx950 device, or a HIP runtime call failed */
+    CT_EMAXSTEPS = -5,  /* step cap reached with holes still drifting */
+    CT_ENONFINITE = -6  /* an explicit position is NaN or infinite */
+} ct_status;
+
+/* Arithmetic of the pairwise field.  Positions and the time integration are
+ * FP64 in both modes.  CT_FP32: the field sum runs in FP32 on coordinates
+ * relative to the event centroid, with per-tile FP32 partial sums folded
+ * into FP64 accumulators. */
+typedef enum { CT_FP64 = 0, CT_FP32 = 1 } ct_precision;
+
+/* Mobility model.  CT_MOB_JACOBONI: mu = mu0 / (1 + (E/Ec)^beta)^(1/beta),
+ * with the Jacoboni-Canali hole laws at T (vm = 1.62e8 T^-0.52 cm/s,
+ * Ec = 1.24 T^1.68 V/cm, beta = 0.46 T^0.17, mu0 = vm/Ec) unless overridden.
+ * CT_MOB_CONSTANT: mu = mu0. */
+typedef enum { CT_MOB_JACOBONI = 0, CT_MOB_CONSTANT = 1 } ct_mobility;
+
+/* physics_flags bits; the paper's method has all three on */
+enum { CT_REPULSION = 1u, CT_DRIFT = 2u, CT_DIFFUSION = 4u };
+
+/* options bits */
+enum {
+    CT_OPT_TIMING = 1u /* time every repulsion-step kernel with HIP events (ct_run_stats) */
+};
+
+typedef struct {
+    uint32_t abi_version;      /* CT_ABI_VERSION */
+    double thickness_um;       /* H > 0 (Algorithm 1 input) */
+    double v_bias;             /* V_bias (Algorithm 1 input) */
+    double v_dep;              /* V_depletion, 0 <= v_dep < v_bias when CT_DRIFT is set (Eq. 6) */
+    double temperature_k;      /* T > 0 (Algorithm 1 input) */
+    double pitch_um;           /* pixel pitch > 0 */
+    int32_t grid_n;            /* pixels per side, 1..64; grid centred on (0, 0) */
+    double dt_ns;              /* time step > 0 */
+    double softening_um;       /* s >= 0 (0 = Eq. 4 exactly) */
+    double eps_r;              /* relative permittivity > 0 (11.7 for silicon) */
+    double pair_energy_ev;     /* energy per electron-hole pair > 0 (3.62 eV in the paper) */
+    int32_t mobility;          /* ct_mobility */
+    double mu0_override;       /* um^2/(V ns); NaN = model value */
+    double ec_override;        /* V/um; NaN = model value */
+    double beta_override;      /* NaN = model value */
+    uint32_t physics_flags;    /* CT_REPULSION | CT_DRIFT | CT_DIFFUSION */
+    int32_t precision;         /* ct_precision */
+    uint64_t seed;             /* Philox4x32-10 key = (low 32 bits, high 32 bits) */
+    int64_t max_steps;         /* default step cap for ct_step (> 0) */
+    void *hip_stream;          /* hipStream_t to issue work on (e.g. torch's); NULL = own stream */
+    int32_t device;            /* HIP device ordinal; -1 = the current device */
+    uint32_t options;          /* CT_OPT_* bits */
+} ct_sensor_params;
+
+/* One event.  Carrier k of the event is placed at deposit (k mod n_deposits)
+ * plus sigma times three standard normals drawn from Philox counter
+ * (id_k, 0, event id, 1); with n_deposits == 0 it is placed at xyz[k].
+ * Positions above the entrance side (z > H) are mirrored to 2H - z; carriers
+ * at z <= 0 are collected at step start_step. */
+typedef struct {
+    double energy_kev;         /* used when n_carriers <= 0 or sigma_um < 0 */
+    int32_t n_carriers;        /* > 0, or <= 0 for round(1000 E / pair_energy_ev) (Algorithm 1) */
+    int32_t n_deposits;        /* >= 1: Gaussian cloud(s); 0: explicit positions */
+    double sigma_um;           /* per-axis width >= 0, or < 0 for 0.0044 E^1.75 (Eq. 2) */
+    const double *deposits;    /* host [n_deposits][3], x y z in um */
+    const double *xyz;         /* host [n_carriers][3] when n_deposits == 0 */
+    const int32_t *ids;        /* host [n_carriers] RNG carrier ids, or NULL for 0..n-1 */
+    int64_t start_step;        /* absolute step of the given state (0 for a new event) */
+} ct_event_desc;
+
+typedef struct {
+    int64_t steps;             /* steps issued by ct_step since seeding */
+    uint64_t pairs;            /* sum over steps and events of N_a (N_a - 1) */
+    int64_t n_total;           /* carriers in the batch */
+    int64_t n_active;          /* carriers still drifting */
+    int64_t field_launches;    /* repulsion-step kernel launches timed (CT_OPT_TIMING) */
+    double field_kernel_ms;    /* their summed duration, HIP events on the context's stream */
+    double step_wall_ms;       /* host wall time spent inside ct_step */
+    int32_t targets_per_thread;/* launch configuration in use */
+    int32_t block_size;
+    int32_t chunk_len;         /* sources per workgroup chunk (events above it are split) */
+    int32_t reserved;
+} ct_run_stats;
+
+/* Create a context for one sensor configuration on one gfx950 device.
+ * Validates every parameter (CT_EINVAL), requires a gfx950 device
+ * (CT_EDEVICE otherwise, also on a host without a GPU). */
+ct_status ct_init_sensor(const ct_sensor_params *p, ct_ctx **out);
+
+/* Carrier count of each event as the library derives it (Algorithm 1:
+ * round(1000 E / w) when n_carriers <= 0).  Host only. */
+ct_status ct_event_carriers(const ct_sensor_params *p, const ct_event_desc *ev, int32_t n_events,
+                            int32_t *n_out);
+
+/* Device bytes ct_seed_events needs for this batch (one buffer). */
+size_t ct_workspace_bytes(const ct_sensor_params *p, const ct_event_desc *ev, int32_t n_events);
+
+/* Use caller-owned device memory (e.g. a torch allocation) for the next
+ * batches instead of library allocations.  NULL unbinds. */
+ct_status ct_bind_workspace(ct_ctx *c, void *device_ptr, size_t bytes);
+
+/* Replace the context's batch by n_events new events (ids first_event_id + b)
+ * and seed their initial clouds on the device (Algorithm 1, initialisation).
+ * Explicit positions that are not finite give CT_ENONFINITE. */
+ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
+                         uint64_t first_event_id);
+
+/* Advance every event until all holes are collected or max_steps steps have
+ * been issued by this call (max_steps <= 0: the context's max_steps).
+ * steps_done (nullable): the most steps any event took in this call;
+ * n_active (nullable): holes still drifting.  Returns CT_OK when none is
+ * left, CT_EMAXSTEPS otherwise (state kept; call again to continue). */
+ct_status ct_step(ct_ctx *c, int64_t max_steps, int64_t *steps_done, int64_t *n_active);
+
+/* Copy results to host arrays (each nullable):
+ *   pixel_counts [B][grid_n*grid_n + 1]  collected holes per pixel, last = outside the grid
+ *   xyz          [N_total][3]            position at collection, or current position if
+ *                                         still drifting; events in order, carriers in
+ *                                         their given order
+ *   collect_step [N_total]               absolute step of collection, -1 = drifting
+ *   event_steps  [B]                     steps each event has taken since seeding
+ *   stats        run statistics */
+ct_status ct_collect(ct_ctx *c, int32_t *pixel_counts, double *xyz, int32_t *collect_step,
+                     int64_t *event_steps, ct_run_stats *stats);
+
+/* Repulsion field (V/um, Eq. 4) that the next step would apply, computed by
+ * the same kernels and precision as ct_step, for every carrier of the batch
+ * ([N_total][3], carrier order); drifting carriers only, NaN for collected. */
+ct_status ct_field(ct_ctx *c, double *field);
+
+/* Philox4x32-10 blocks and the Box-Muller normals the kernels derive from
+ * them, for n host counters [n][4] under the context's seed:
+ * words [n][4] (nullable), normals [n][3] (nullable). */
+ct_status ct_philox(ct_ctx *c, const uint32_t *counters, int64_t n, uint32_t *words,
+                    double *normals);
+
+/* Override the launch configuration (targets per thread 1, 2 or 4; block
+ * size 64..1024, multiple of 64; chunk_len >= block size, multiple of it,
+ * or 0 for no source splitting).  0 leaves a value unchanged. */
+ct_status ct_set_launch(ct_ctx *c, int32_t targets_per_thread, int32_t block_size,
+                        int32_t chunk_len);
+
+void ct_destroy(ct_ctx *c);
+
+const char *ct_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CT_H */

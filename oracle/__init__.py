@@ -75,6 +75,8 @@ def lib():
         L.oc_drift_field.argtypes = [C.POINTER(OcParams), C.c_double]
         L.oc_drift_field.restype = C.c_double
         L.oc_field.argtypes = [C.POINTER(OcParams), C.c_int64, dp, dp]
+        L.oc_field_targets.argtypes = [C.POINTER(OcParams), C.c_int64, dp, C.c_int64,
+                                       C.POINTER(C.c_int64), dp]
         L.oc_carrier_count.argtypes = [C.POINTER(OcParams), C.POINTER(OcEvent)]
         L.oc_carrier_count.restype = C.c_int32
         L.oc_initial_sigma.argtypes = [C.POINTER(OcEvent)]
@@ -157,6 +159,16 @@ def field(sensor, xyz: np.ndarray) -> np.ndarray:
     xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
     E = np.zeros_like(xyz)
     lib().oc_field(C.byref(params(sensor)), xyz.shape[0], _dp(xyz), _dp(E))
+    return E
+
+
+def field_at(sensor, xyz: np.ndarray, targets) -> np.ndarray:
+    """Repulsion field on the listed carriers only ([len(targets), 3])."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    t = np.ascontiguousarray(targets, dtype=np.int64)
+    E = np.zeros((len(t), 3))
+    lib().oc_field_targets(C.byref(params(sensor)), xyz.shape[0], _dp(xyz), len(t),
+                           t.ctypes.data_as(C.POINTER(C.c_int64)), _dp(E))
     return E
 
 

@@ -214,6 +214,27 @@ void oc_field(const oc_params *p, int64_t n, const double *xyz, double *E)
     free(z);
 }
 
+/* Repulsion field on selected carriers only: E[t] for carrier targets[t] of
+ * the n carriers in xyz (each target costs O(n)). */
+void oc_field_targets(const oc_params *p, int64_t n, const double *xyz, int64_t n_t,
+                      const int64_t *targets, double *E)
+{
+    double *x = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *y = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *z = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        x[i] = xyz[3 * i];
+        y[i] = xyz[3 * i + 1];
+        z[i] = xyz[3 * i + 2];
+    }
+    const double K = oc_coulomb_k(p);
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < n_t; ++t) repulsion_one(p, n, x, y, z, targets[t], K, E + 3 * t);
+    free(x);
+    free(y);
+    free(z);
+}
+
 /* Algorithm 1, initialisation: N = round(E / w) carriers. */
 int32_t oc_carrier_count(const oc_params *p, const oc_event *ev)
 {

@@ -1,0 +1,398 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances:
+  * integer results (collection steps, pixel counts, pair counts) are exact;
+  * FP64 mode: per-carrier endpoints within 0.01 um of the oracle;
+  * FP32 mode: pixel charge fractions within 1e-3 absolute of the oracle;
+  * repulsion field at a fixed state: within an error bound derived from the
+    arithmetic of each mode (see field_error_bound).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import (Batch, Sensor, batch_8kev, explicit_batch, gamma_60kev, mixed_energy,
+                       single_8kev, track_200kev)
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+ENDPOINT_TOL_UM = 0.01
+FRACTION_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def ct():
+    import paper_2506_09712_amd as ct
+    ct.load()
+    oracle.build(force=False)
+    return ct
+
+
+def gpu_run(ct, sensor, batch, precision, launch=None, max_steps=0):
+    with ct.Simulator(sensor, precision, launch=launch) as sim:
+        r = sim.run(batch, max_steps)
+    return r
+
+
+def fractions(r):
+    n = r["pix"].sum(axis=1, keepdims=True)
+    return r["pix"] / np.maximum(n, 1)
+
+
+def check_conservation(r, batch_n):
+    np.testing.assert_array_equal(r["pix"].sum(axis=1), batch_n)
+
+
+def assert_fp64_parity(g, o, tag=""):
+    assert g["status"] == o["status"], tag
+    np.testing.assert_array_equal(g["cstep"], o["cstep"], err_msg=f"collect steps {tag}")
+    err = np.abs(g["xyz"] - o["xyz"]).max() if len(g["xyz"]) else 0.0
+    assert err <= ENDPOINT_TOL_UM, f"{tag}: max endpoint error {err} um"
+    np.testing.assert_array_equal(g["pix"], o["pix"], err_msg=f"pixel counts {tag}")
+    return err
+
+
+def assert_fp32_parity(g, o, tag=""):
+    assert g["status"] == o["status"], tag
+    df = np.abs(fractions(g) - fractions(o)).max()
+    assert df <= FRACTION_TOL, f"{tag}: max pixel-fraction error {df}"
+    return df
+
+
+def endpoint_error_stats(g, o):
+    e = np.linalg.norm(g["xyz"][:, :2] - o["xyz"][:, :2], axis=1)
+    return {"max": float(e.max()), "p99": float(np.percentile(e, 99)), "mean": float(e.mean())}
+
+
+# ------------------------------------------------------------------ RNG
+
+def test_philox_words_bitwise_and_normals(ct):
+    rng = np.random.default_rng(11)
+    ctr = rng.integers(0, 2**32, size=(20000, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:4] = [[0, 0, 0, 0], [2**32 - 1] * 4, [5, 0, 3, 1], [1, 2, 3, 0]]
+    s = Sensor(seed=0x1234_5678_9ABC_DEF0)
+    with ct.Simulator(s, FP64) as sim:
+        words, normals = ct.ct_philox(sim.ctx, ctr)
+    key = (s.seed & 0xFFFFFFFF, s.seed >> 32)
+    ref = np.array([oracle.philox(c, key) for c in ctr])
+    np.testing.assert_array_equal(words, ref)
+    refn = np.array([oracle.normals3(s.seed, *map(int, c)) for c in ctr[:4000]])
+    np.testing.assert_allclose(normals[:4000], refn, rtol=0, atol=1e-13)
+
+
+# ------------------------------------------------------------ seeding
+
+def test_seeding_matches_oracle(ct):
+    s = Sensor(seed=3)
+    _, tb = track_200kev(n_events=1, seed=5)
+    rng = np.random.default_rng(4)
+    ex = rng.normal(size=(50, 3)) * 2 + [0, 0, 40.0]
+    ex[:3, 2] = [-1.0, 0.0, s.thickness_um + 2.0]   # collected, collected, mirrored
+    b = Batch(energy_kev=[8.0, 200.0, 0.0], n_carriers=[500, 4000, 50], sigma_um=[1.0, 0.5, 0.0],
+              n_deposits=[1, 40, 0], deposits=np.vstack([[[3.0, -2.0, 319.5]], tb.deposits]),
+              xyz=ex, first_event_id=7)
+    for prec in (FP64, FP32):
+        with ct.Simulator(s.replace(max_steps=1), prec) as sim:
+            sim.seed(b)
+            g = sim.collect()
+        o = oracle.run(s.replace(max_steps=0), b)
+        np.testing.assert_array_equal(g["cstep"], o["cstep"])
+        np.testing.assert_array_equal(g["pix"], o["pix"])
+        np.testing.assert_allclose(g["xyz"], o["xyz"], rtol=0, atol=1e-11)
+
+
+# ------------------------------------------------------ field at a state
+
+def field_error_bound(xyz, soft, K, fp32, tile=256):
+    """Per-carrier bound on |E_gpu - E_exact| from the arithmetic of the mode.
+
+    FP32: coordinates are rounded to FP32 relative to the centroid (error
+    <= u rho per component, rho = the largest centroid distance), the
+    difference itself rounds (u |d|), and t(d) = d/(|d|^2+s^2)^(3/2) has
+    |dt/dd| <= 2/(|d|^2+s^2)^(3/2); each term is evaluated with a few
+    roundings (<= 8u |t|) and summed in FP32 over a tile (<= tile u sum|t|).
+    FP64: the same with u = 2^-53 and exact coordinates.
+    """
+    u = 2.0**-24 if fp32 else 2.0**-53
+    c = xyz.mean(axis=0)
+    rho = np.abs(xyz - c).max() if fp32 else 0.0
+    d = xyz[:, None, :] - xyz[None, :, :]
+    r2 = (d**2).sum(-1) + max(soft * soft, 1e-20)
+    r = np.sqrt((d**2).sum(-1))
+    w = r2**-1.5
+    np.fill_diagonal(w, 0.0)
+    dd = math.sqrt(3) * (2 * u * rho + u * r)
+    tabs = r * w
+    bound = K * ((2 * w * dd).sum(1) + (8 * u + tile * u + len(xyz) * (0 if fp32 else u)) * tabs.sum(1))
+    return bound
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 255, 256, 257, 1000, 2222])
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_field_matches_oracle(ct, n, prec):
+    rng = np.random.default_rng(n)
+    xyz = rng.normal(size=(n, 3)) * [1.0, 1.5, 0.8] + [4.0, -3.0, 120.0]
+    s = Sensor(softening_um=0.01)
+    K = oracle.coulomb_k(s)
+    ref = oracle.field(s, xyz)
+    bound = field_error_bound(xyz, s.softening_um, K, prec == FP32)
+    for launch in [None, (1, 128, 0), (4, 256, 0), (2, 128, 256)]:
+        with ct.Simulator(s, prec, launch=launch) as sim:
+            sim.seed(explicit_batch([xyz]))
+            E = sim.field()
+        err = np.abs(E - ref).max(axis=1)
+        assert np.all(err <= bound + 1e-300), (launch, (err / np.maximum(bound, 1e-300)).max())
+
+
+def test_field_zero_sum_and_retired_are_nan(ct):
+    rng = np.random.default_rng(3)
+    xyz = rng.normal(size=(900, 3)) + [0, 0, 60.0]
+    xyz[:5, 2] = -1.0  # collected at seeding
+    for prec, tol in ((FP64, 1e-13), (FP32, 1e-6)):
+        with ct.Simulator(Sensor(), prec) as sim:
+            sim.seed(explicit_batch([xyz]))
+            E = sim.field()
+        assert np.all(np.isnan(E[:5]))
+        Ea = E[5:]
+        assert np.abs(Ea.sum(axis=0)).max() <= tol * np.abs(Ea).sum(), prec
+
+
+# ------------------------------------------------------ full-run parity
+
+def test_single_8kev_fp64(ct):
+    s, b = single_8kev(seed=0)
+    o = oracle.run(s, b)
+    g = gpu_run(ct, s, b, FP64)
+    err = assert_fp64_parity(g, o, "single_8kev fp64")
+    assert g["pairs"] == o["pairs"] and np.array_equal(g["steps"], o["steps"])
+    print(f"single_8kev fp64: max endpoint error {err:.3e} um, steps {o['steps'][0]}")
+
+
+def test_single_8kev_fp32(ct):
+    s, b = single_8kev(seed=0)
+    o = oracle.run(s, b)
+    g = gpu_run(ct, s, b, FP32)
+    df = assert_fp32_parity(g, o, "single_8kev fp32")
+    check_conservation(g, [2222])
+    print(f"single_8kev fp32: fraction error {df:.2e}, endpoint error {endpoint_error_stats(g, o)}")
+
+
+@pytest.fixture(scope="module")
+def batch256(ct):
+    s, b = batch_8kev(n_events=256, seed=0)
+    g64 = gpu_run(ct, s, b, FP64)
+    g32 = gpu_run(ct, s, b, FP32)
+    return s, b, g64, g32
+
+
+SAMPLED = [0, 1, 77, 128, 200, 255]
+
+
+def _event_slice(r, b):
+    off = r["offsets"]
+    return {"status": r["status"], "pix": r["pix"][b:b + 1], "xyz": r["xyz"][off[b]:off[b + 1]],
+            "cstep": r["cstep"][off[b]:off[b + 1]]}
+
+
+def test_batch_8kev_sampled_events(ct, batch256):
+    s, b, g64, g32 = batch256
+    check_conservation(g64, b.n_carriers)
+    check_conservation(g32, b.n_carriers)
+    worst64, worst32 = 0.0, 0.0
+    for e in SAMPLED:
+        o = oracle.run(s, b.event(e))
+        worst64 = max(worst64, assert_fp64_parity(_event_slice(g64, e), o, f"event {e} fp64"))
+        worst32 = max(worst32, assert_fp32_parity(_event_slice(g32, e), o, f"event {e} fp32"))
+    # whole-batch properties: FP32 vs FP64 paths agree on every event
+    df = np.abs(fractions(g32) - fractions(g64)).max()
+    assert df <= 2 * FRACTION_TOL
+    print(f"batch_8kev: fp64 worst endpoint {worst64:.2e} um; fp32 worst fraction {worst32:.2e}; "
+          f"fp32 vs fp64 all 256 events {df:.2e}")
+
+
+@pytest.mark.parametrize("launch", [None, (1, 128, 0), (2, 256, 0), (4, 256, 0), (4, 128, 0),
+                                    (2, 256, 256), (1, 128, 384)])
+def test_ragged_batch_all_launches(ct, launch):
+    rng = np.random.default_rng(21)
+    sizes = [0, 1, 2, 63, 64, 65, 300, 1025]
+    evs = [rng.normal(size=(n, 3)) * 1.2 + [rng.uniform(-10, 10), rng.uniform(-10, 10),
+                                             rng.uniform(5, 60)] for n in sizes]
+    s = Sensor(seed=9)
+    b = explicit_batch(evs, first_event_id=100)
+    o = oracle.run(s, b)
+    g = gpu_run(ct, s, b, FP64, launch=launch)
+    assert_fp64_parity(g, o, f"ragged fp64 {launch}")
+    g32 = gpu_run(ct, s, b, FP32, launch=launch)
+    assert_fp32_parity(g32, o, f"ragged fp32 {launch}")
+    check_conservation(g32, sizes)
+
+
+def test_mixed_energy_sampled(ct):
+    """Uneven batch (1667..6111 holes) in one launch; oracle on sampled events."""
+    s, b = mixed_energy(n_events=1024, seed=0)
+    g32 = gpu_run(ct, s, b, FP32)
+    check_conservation(g32, b.n_carriers)
+    picks = [int(np.flatnonzero(b.n_carriers == n)[0]) for n in (1667, 6111)]
+    for e in picks:
+        o = oracle.run(s, b.event(e))
+        assert_fp32_parity(_event_slice(g32, e), o, f"mixed event {e}")
+
+
+def _bound_at(xyz, targets, soft, K, fp32, tile=256):
+    """field_error_bound restricted to sampled targets (O(targets x N))."""
+    u = 2.0**-24 if fp32 else 2.0**-53
+    rho = np.abs(xyz - xyz.mean(axis=0)).max() if fp32 else 0.0
+    out = np.zeros(len(targets))
+    for k, i in enumerate(targets):
+        d = xyz[i] - xyz
+        r = np.sqrt((d**2).sum(-1))
+        w = (r**2 + max(soft * soft, 1e-20)) ** -1.5
+        w[i] = 0.0
+        dd = math.sqrt(3) * (2 * u * rho + u * r)
+        out[k] = K * ((2 * w * dd).sum() + (8 * u + tile * u + len(xyz) * (0 if fp32 else u))
+                      * (r * w).sum())
+    return out
+
+
+@pytest.mark.parametrize("make", [gamma_60kev, track_200kev])
+def test_large_events_full_size(ct, make):
+    """60 keV (16,667 holes) and 200 keV-track (55,556 holes) events at full
+    size: the seeded state's field on sampled targets (oracle one target at a
+    time) in both precisions, FP64 positions after 3 steps against the
+    oracle, and FP32 vs FP64 pixel fractions over complete runs."""
+    s, b = make(n_events=2, seed=0)
+    ev = b.event(1)
+    K = oracle.coulomb_k(s)
+    with ct.Simulator(s.replace(max_steps=1), FP64) as sim:
+        sim.seed(ev)
+        x0 = sim.collect()["xyz"]
+    rng = np.random.default_rng(1)
+    tg = np.sort(rng.choice(len(x0), size=300, replace=False))
+    ref = oracle.field_at(s, x0, tg)
+    for prec in (FP64, FP32):
+        with ct.Simulator(s, prec) as sim:
+            sim.seed(ev)
+            E = sim.field()[tg]
+        bound = _bound_at(x0, tg, s.softening_um, K, prec == FP32)
+        err = np.abs(E - ref).max(axis=1)
+        assert np.all(err <= bound), (make.__name__, prec, (err / bound).max())
+    o = oracle.run(s.replace(max_steps=3), ev)
+    g = gpu_run(ct, s.replace(max_steps=3), ev, FP64)
+    assert g["status"] == -5 and o["status"] == -5
+    assert np.abs(g["xyz"] - o["xyz"]).max() <= 1e-9
+    np.testing.assert_array_equal(g["cstep"], o["cstep"])
+    g32 = gpu_run(ct, s.replace(max_steps=3), ev, FP32)
+    print(f"{make.__name__}: FP32 position error after 3 steps "
+          f"{np.abs(g32['xyz'] - o['xyz']).max():.2e} um")
+    full64 = gpu_run(ct, s, b, FP64)
+    full32 = gpu_run(ct, s, b, FP32)
+    check_conservation(full64, b.n_carriers)
+    check_conservation(full32, b.n_carriers)
+    df = np.abs(fractions(full32) - fractions(full64)).max()
+    assert df <= FRACTION_TOL, (make.__name__, df)
+    print(f"{make.__name__}: FP32 vs FP64 pixel fractions over full runs: {df:.2e}")
+
+
+# ------------------------------------------------------ closed forms
+
+def test_closed_forms_through_abi(ct):
+    import scipy.constants as sc
+    K = sc.e / (4 * math.pi * sc.epsilon_0 * 11.7) * 1e6
+    mu0 = 48.0
+    for prec in (FP64, FP32):
+        # uniform-field drift: collection step = ceil(z0 / (v dt))
+        s = Sensor(v_dep=0.0, repulsion=False, diffusion=False, mobility="constant", mu0_override=mu0)
+        z0 = np.array([50.3, 123.456, 7.77, 319.0])
+        g = gpu_run(ct, s, explicit_batch([np.column_stack([np.zeros(4), np.ones(4), z0])]), prec)
+        v = mu0 * s.v_bias / s.thickness_um
+        np.testing.assert_array_equal(g["cstep"], np.ceil(z0 / (v * s.dt_ns)).astype(int))
+        # two charges: r^3 = r0^3 + 6 mu0 K t
+        s = Sensor(drift=False, diffusion=False, mobility="constant", mu0_override=mu0,
+                   softening_um=0.0, dt_ns=0.01, max_steps=1000)
+        g = gpu_run(ct, s, explicit_batch([[[-0.5, 0, 100.0], [0.5, 0, 100.0]]]), prec)
+        r = g["xyz"][1, 0] - g["xyz"][0, 0]
+        assert abs(r - (1 + 6 * mu0 * K * 10.0) ** (1 / 3)) < 1e-4
+        # tetrahedron: R^3 = R0^3 + 3 mu0 K C t, shape kept
+        V = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]]) / math.sqrt(3)
+        C = 0.5 * np.sum(1 / np.linalg.norm(V[0] - V[1:], axis=1))
+        g = gpu_run(ct, s, explicit_batch([V + [0, 0, 100.0]]), prec)
+        R = np.linalg.norm(g["xyz"] - [0, 0, 100.0], axis=1)
+        exact = (1 + 3 * mu0 * K * C * 10.0) ** (1 / 3)
+        assert np.all(np.abs(R - exact) / exact < 1e-4)
+        assert np.ptp(R) < (1e-12 if prec == FP64 else 1e-5) * exact
+
+
+# ------------------------------------------------------ invariants
+
+def test_batch_equals_alone_bitwise(ct):
+    s, b = batch_8kev(n_events=4, seed=2)
+    b = Batch(b.energy_kev, [600, 900, 300, 1200], b.sigma_um, b.n_deposits, b.deposits,
+              first_event_id=40)
+    for prec in (FP64, FP32):
+        g = gpu_run(ct, s, b, prec)
+        for e in range(4):
+            a = gpu_run(ct, s, b.event(e), prec)
+            sl = _event_slice(g, e)
+            np.testing.assert_array_equal(a["xyz"], sl["xyz"])
+            np.testing.assert_array_equal(a["cstep"], sl["cstep"])
+            np.testing.assert_array_equal(a["pix"], sl["pix"])
+
+
+def test_run_to_run_bitwise_and_continue(ct):
+    s, b = batch_8kev(n_events=6, seed=4)
+    for prec in (FP64, FP32):
+        g1 = gpu_run(ct, s, b, prec)
+        g2 = gpu_run(ct, s, b, prec)
+        np.testing.assert_array_equal(g1["xyz"], g2["xyz"])
+        np.testing.assert_array_equal(g1["pix"], g2["pix"])
+        with ct.Simulator(s, prec) as sim:  # interrupted by the step cap, then continued
+            sim.seed(b)
+            st, done, act = sim.step(37)
+            assert st == -5 and done == 37 and act > 0
+            st, done, act = sim.step(0)
+            assert st == 0 and act == 0
+            g3 = sim.collect()
+        np.testing.assert_array_equal(g1["xyz"], g3["xyz"])
+        np.testing.assert_array_equal(g1["cstep"], g3["cstep"])
+
+
+def test_resume_from_exported_state(ct):
+    """Checkpoint/resume: the drifting holes' positions, carrier ids and step
+    re-seeded as an explicit event continue exactly as the uninterrupted run."""
+    s, b = single_8kev(seed=1)
+    b = Batch(b.energy_kev, [800], b.sigma_um, b.n_deposits, b.deposits)
+    full = gpu_run(ct, s, b, FP64)
+    with ct.Simulator(s, FP64) as sim:
+        sim.seed(b)
+        sim.step(12)
+        part = sim.collect()
+    alive = np.flatnonzero(part["cstep"] < 0)
+    rb = explicit_batch([part["xyz"][alive]], start_step=[12])
+    with ct.Simulator(s, FP64) as sim:
+        sim.seed(rb, ids=[alive])
+        st, _, _ = sim.step(0)
+        res = sim.collect()
+    assert st == 0
+    np.testing.assert_array_equal(res["xyz"], full["xyz"][alive])
+    np.testing.assert_array_equal(res["cstep"], full["cstep"][alive])
+    done = part["pix"] + res["pix"]
+    np.testing.assert_array_equal(done, full["pix"])
+
+
+def test_error_paths(ct):
+    s = Sensor()
+    with ct.Simulator(s, FP64) as sim:
+        with pytest.raises(ct.CtError) as e:
+            ct.ct_step(sim.ctx, 5)
+        assert e.value.status == -2  # CT_ESTATE
+        with pytest.raises(ct.CtError) as e:
+            sim.seed(explicit_batch([[[0.0, float("nan"), 10.0]]]))
+        assert e.value.status == -6  # CT_ENONFINITE
+        sim.seed(explicit_batch([]))  # empty batch
+        assert sim.step(0)[0] == 0
+        sim.seed(explicit_batch([np.zeros((0, 3)), [[0, 0, -1.0]]]))
+        r = sim.collect()
+        assert r["pix"][1].sum() == 1 and r["pix"][0].sum() == 0
