@@ -74,7 +74,11 @@ enum { CT_REPULSION = 1u, CT_DRIFT = 2u, CT_DIFFUSION = 4u };
 
 /* options bits */
 enum {
-    CT_OPT_TIMING = 1u /* time every repulsion-step kernel with HIP events (ct_run_stats) */
+    CT_OPT_TIMING = 1u,  /* time every repulsion-step kernel with HIP events (ct_run_stats) */
+    CT_OPT_NO_GRAPH = 2u, /* issue every step eagerly instead of replaying a captured graph */
+    CT_OPT_AUTOTUNE = 4u  /* on seeding, time the launch configurations on the seeded state and
+                             keep the fastest (cached per precision and batch-shape bucket);
+                             the chosen configuration sets the summation order of the field */
 };
 
 typedef struct {

@@ -31,6 +31,8 @@ CT_FP64, CT_FP32 = 0, 1
 CT_MOB_JACOBONI, CT_MOB_CONSTANT = 0, 1
 CT_REPULSION, CT_DRIFT, CT_DIFFUSION = 1, 2, 4
 CT_OPT_TIMING = 1
+CT_OPT_NO_GRAPH = 2
+CT_OPT_AUTOTUNE = 4
 
 _STATUS = {0: "CT_OK", -1: "CT_EINVAL", -2: "CT_ESTATE", -3: "CT_ENOMEM", -4: "CT_EDEVICE",
            -5: "CT_EMAXSTEPS", -6: "CT_ENONFINITE"}
@@ -207,18 +209,22 @@ def ct_step(ctx, max_steps: int = 0):
     return st, int(done.value), int(act.value)
 
 
-def ct_collect(ctx, n_events: int, n_total: int, grid_n: int):
+def ct_collect(ctx, n_events: int, n_total: int, grid_n: int, carriers: bool = True):
+    """Pixel counts, event steps and stats; with carriers=True also the
+    per-carrier positions and collection steps (else those are None)."""
     G1 = grid_n * grid_n + 1
     pix = np.zeros((max(n_events, 1), G1), dtype=np.int32)
-    xyz = np.zeros((max(n_total, 1), 3), dtype=np.float64)
-    cstep = np.zeros(max(n_total, 1), dtype=np.int32)
+    xyz = np.zeros((max(n_total, 1), 3), dtype=np.float64) if carriers else None
+    cstep = np.zeros(max(n_total, 1), dtype=np.int32) if carriers else None
     esteps = np.zeros(max(n_events, 1), dtype=np.int64)
     stats = ct_run_stats()
     _check(load().ct_collect(ctx, pix.ctypes.data_as(C.POINTER(C.c_int32)), _dp(xyz),
-                             cstep.ctypes.data_as(C.POINTER(C.c_int32)),
+                             cstep.ctypes.data_as(C.POINTER(C.c_int32)) if carriers else None,
                              esteps.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(stats)),
            "ct_collect")
-    return pix[:n_events], xyz[:n_total], cstep[:n_total], esteps[:n_events], stats
+    if carriers:
+        xyz, cstep = xyz[:n_total], cstep[:n_total]
+    return pix[:n_events], xyz, cstep, esteps[:n_events], stats
 
 
 def ct_field(ctx, n_total: int) -> np.ndarray:
@@ -257,7 +263,8 @@ class Simulator:
     allocation bound with ct_bind_workspace.
     """
 
-    def __init__(self, sensor, precision: int = CT_FP64, device: int = 0, use_torch: Optional[bool] = None,
+    def __init__(self, sensor, precision: int = CT_FP64, device: int = 0,
+                 use_torch: Optional[bool] = None,
                  options: int = 0, launch: Optional[tuple] = None):
         self.sensor = sensor
         self.precision = precision
@@ -271,6 +278,8 @@ class Simulator:
         self.params = make_params(sensor, precision, stream=stream, device=device, options=options)
         self.ctx = ct_init_sensor(self.params)
         self._ws = None
+        self._descs = None
+        self._descs_of = None
         if launch:
             ct_set_launch(self.ctx, *launch)
         self.batch = None
@@ -297,7 +306,10 @@ class Simulator:
         ct_set_launch(self.ctx, targets_per_thread, block_size, chunk_len)
 
     def seed(self, batch, ids=None):
-        descs = EventDescs(batch, ids)
+        if ids is None and self._descs is not None and self._descs_of is batch:
+            descs = self._descs  # same batch object: reuse its marshalled descriptions
+        else:
+            descs = EventDescs(batch, ids)
         self.counts = ct_event_carriers(self.params, descs)
         if self.use_torch:
             nbytes = ct_workspace_bytes(self.params, descs) + (1 << 20)
@@ -309,13 +321,14 @@ class Simulator:
         self.batch = batch
         self.n_total = int(self.counts.sum())
         self._descs = descs
+        self._descs_of = batch if ids is None else None
 
     def step(self, max_steps: int = 0):
         return ct_step(self.ctx, max_steps)
 
-    def collect(self) -> dict:
+    def collect(self, carriers: bool = True) -> dict:
         pix, xyz, cstep, esteps, stats = ct_collect(self.ctx, self.batch.n_events, self.n_total,
-                                                    self.sensor.grid_n)
+                                                    self.sensor.grid_n, carriers)
         off = np.zeros(self.batch.n_events + 1, dtype=np.int64)
         np.cumsum(self.counts, out=off[1:])
         return {"pix": pix, "xyz": xyz, "cstep": cstep, "steps": esteps, "pairs": int(stats.pairs),

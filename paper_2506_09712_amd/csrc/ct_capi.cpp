@@ -9,8 +9,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ct.h"
@@ -130,7 +133,7 @@ double initial_sigma(const ct_event_desc &e)
 // Byte layout of one batch inside a single device buffer.
 struct Layout {
     size_t off, n_act, ev_step, ev_taken, ref, pos, idx, rngid, out_xyz, out_cstep, pix, pairs,
-        active2, sigma, dep_off, deposits, x_off, xyz_in, start, total;
+        active, item_base, n_items, counter, sigma, dep_off, deposits, x_off, xyz_in, start, total;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -156,7 +159,10 @@ Layout make_layout(int64_t B, int64_t N, int64_t n_dep, int64_t n_exp, int G1)
     L.out_cstep = take(sizeof(int32_t) * N);
     L.pix = take(sizeof(int32_t) * B * G1);
     L.pairs = take(sizeof(uint64_t) * B);
-    L.active2 = take(sizeof(int64_t) * 2);
+    L.active = take(sizeof(int64_t));
+    L.item_base = take(sizeof(int32_t) * B);
+    L.n_items = take(sizeof(int32_t));
+    L.counter = take(sizeof(uint32_t));
     L.sigma = take(sizeof(double) * B);
     L.dep_off = take(sizeof(int32_t) * (B + 1));
     L.deposits = take(sizeof(double) * 3 * n_dep);
@@ -206,8 +212,12 @@ ct_status shape_of(const ct_sensor_params &p, const ct_event_desc *ev, int32_t B
 // Launch configuration of a new context (ct_set_launch overrides it).
 ct::LaunchCfg default_cfg(const ct_sensor_params &p)
 {
-    return p.precision == CT_FP32 ? ct::LaunchCfg{2, 256, 0} : ct::LaunchCfg{1, 256, 0};
+    // measured best on 256 events of 2222 holes (one target per thread,
+    // 256-thread workgroups, sources split into chunks of <= 768 / 512)
+    return p.precision == CT_FP32 ? ct::LaunchCfg{1, 256, 768} : ct::LaunchCfg{1, 256, 512};
 }
+
+constexpr int kGraphSteps = 16;  // steps per captured graph (and per host poll)
 
 int default_chunks(int chunk, int32_t n_max)
 {
@@ -235,14 +245,23 @@ struct ct_ctx {
     size_t field_buf_n = 0;
     double *part_buf = nullptr;  // partial fields of split events (library-owned)
     size_t part_cap = 0;         // doubles
+    ct::Item *work_buf = nullptr;  // step work list (library-owned)
+    size_t work_cap = 0;
+    int cu_count = 0;
+    int grid = 0;                // persistent step-kernel workgroups for cfg
+
+    // captured step loop, reused while the batch layout and launch are unchanged
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    ct::DevBatch graph_bt{};
+    ct::LaunchCfg graph_cfg{};
+    int graph_grid = 0;
 
     // batch
     bool seeded = false;
     Layout L{};
     ct::DevBatch bt{};
     BatchShape shape;
-    int parity = 0;
-    int32_t n_max_live = 0;
     int64_t n_active = 0;
     int64_t steps = 0;
 
@@ -310,6 +329,39 @@ ct_status ensure_part(ct_ctx *c, const ct::LaunchCfg &cfg, int64_t N, int32_t n_
     return CT_OK;
 }
 
+int64_t work_items_for(const ct::LaunchCfg &cfg, const std::vector<int32_t> &n)
+{
+    const int64_t T = (int64_t)cfg.bs * cfg.kt;
+    int64_t items = 0;
+    for (int32_t v : n)
+        if (v > 0) items += ((v + T - 1) / T) * (cfg.chunk > 0 ? (v + cfg.chunk - 1) / cfg.chunk : 1);
+    return items;
+}
+
+// Work-list buffer sized for the batch's initial sizes (holes only retire,
+// so later steps need fewer items) and the persistent grid for cfg.
+ct_status ensure_work(ct_ctx *c, const ct::LaunchCfg &cfg, const std::vector<int32_t> &n)
+{
+    const int64_t need = std::max<int64_t>(work_items_for(cfg, n), 1);
+    if (need > INT32_MAX) return fail(CT_EINVAL, "work list too long (%lld items)", (long long)need);
+    if ((size_t)need > c->work_cap) {
+        if (c->work_buf) CT_HIP(hipFree(c->work_buf));
+        c->work_buf = nullptr;
+        c->work_cap = 0;
+        if (hipMalloc((void **)&c->work_buf, need * sizeof(ct::Item)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CT_ENOMEM, "work list of %lld items failed", (long long)need);
+        }
+        c->work_cap = (size_t)need;
+    }
+    const int occ = ct::step_occupancy(cfg, c->p.precision == CT_FP32);
+    if (occ <= 0) return fail(CT_EDEVICE, "step kernel occupancy query failed");
+    c->grid = occ * c->cu_count;
+    c->bt.work = c->work_buf;
+    c->bt.work_cap = (int32_t)c->work_cap;
+    return CT_OK;
+}
+
 template <class T>
 T *at(void *base, size_t off)
 {
@@ -324,24 +376,156 @@ ct_status set_device(ct_ctx *c)
 
 ct_status sync_active(ct_ctx *c)
 {
-    CT_HIP(hipMemcpyAsync(c->h_pinned, c->bt.active2 + c->parity, sizeof(int64_t),
-                          hipMemcpyDeviceToHost, c->stream));
+    CT_HIP(hipMemcpyAsync(c->h_pinned, c->bt.active, sizeof(int64_t), hipMemcpyDeviceToHost,
+                          c->stream));
     CT_HIP(hipStreamSynchronize(c->stream));
     c->n_active = c->h_pinned[0];
     return CT_OK;
 }
 
-ct_status refresh_n_max(ct_ctx *c)
+ct_status drop_graph(ct_ctx *c)
 {
-    std::vector<int32_t> na(c->shape.B);
-    if (c->shape.B > 0) {
-        CT_HIP(hipMemcpyAsync(na.data(), c->bt.n_act, sizeof(int32_t) * c->shape.B,
-                              hipMemcpyDeviceToHost, c->stream));
-        CT_HIP(hipStreamSynchronize(c->stream));
+    if (c->graph_exec) CT_HIP(hipGraphExecDestroy(c->graph_exec));
+    if (c->graph) CT_HIP(hipGraphDestroy(c->graph));
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    return CT_OK;
+}
+
+// One time step: work list, pair kernel (+ partial-sum update), compaction.
+// With timing, HIP events bracket the pair kernel (slot i of the event pool).
+hipError_t issue_step(ct_ctx *c, const ct::LaunchCfg &cfg, int slot, bool timing)
+{
+    const int fp32 = c->p.precision == CT_FP32;
+    hipError_t e = ct::launch_plan(c->bt, cfg, c->stream);
+    if (e == hipSuccess && timing) e = hipEventRecord(c->ev_a[slot], c->stream);
+    if (e == hipSuccess) e = ct::launch_step(c->dp, c->bt, cfg, fp32, c->grid, 0, nullptr, c->stream);
+    if (e == hipSuccess && timing) e = hipEventRecord(c->ev_b[slot], c->stream);
+    if (e == hipSuccess) e = ct::launch_update(c->dp, c->bt, cfg, c->shape.n_max, 0, nullptr, c->stream);
+    if (e == hipSuccess) e = ct::launch_compact(c->dp, c->bt, 1, c->stream);
+    return e;
+}
+
+// Capture kGraphSteps steps into one executable graph (per batch and launch
+// configuration); every kernel reads its sizes from device memory, so the
+// same graph serves every chunk of the run.
+ct_status ensure_graph(ct_ctx *c, const ct::LaunchCfg &cfg)
+{
+    if (c->graph_exec && std::memcmp(&c->graph_bt, &c->bt, sizeof c->bt) == 0 &&
+        c->graph_cfg.kt == cfg.kt && c->graph_cfg.bs == cfg.bs && c->graph_cfg.chunk == cfg.chunk &&
+        c->graph_grid == c->grid)
+        return CT_OK;
+    ct_status st = drop_graph(c);
+    if (st != CT_OK) return st;
+    CT_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < kGraphSteps && e == hipSuccess; ++i) e = issue_step(c, cfg, i, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(CT_EDEVICE, "step-loop capture failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    int32_t m = 0;
-    for (int32_t v : na) m = std::max(m, v);
-    c->n_max_live = m;
+    c->graph = g;
+    CT_HIP(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+    c->graph_bt = c->bt;
+    c->graph_cfg = cfg;
+    c->graph_grid = c->grid;
+    return CT_OK;
+}
+
+ct_status ensure_field_buf(ct_ctx *c, int64_t N)
+{
+    if (c->field_buf_n >= (size_t)N) return CT_OK;
+    if (c->field_buf) CT_HIP(hipFree(c->field_buf));
+    c->field_buf = nullptr;
+    c->field_buf_n = 0;
+    if (hipMalloc((void **)&c->field_buf, sizeof(double) * 3 * std::max<int64_t>(N, 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CT_ENOMEM, "field buffer allocation failed");
+    }
+    c->field_buf_n = (size_t)N;
+    return CT_OK;
+}
+
+// Launch configurations chosen by the autotuner, per precision and batch
+// shape bucket (events, largest event, total holes; powers of two).
+using TuneKey = std::tuple<int, int, int, int, int>;
+std::map<TuneKey, ct::LaunchCfg> g_tuned;
+std::mutex g_tuned_mu;
+
+int log2_bucket(int64_t v)
+{
+    int b = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+// Time one field evaluation of the seeded state per candidate (work list,
+// persistent pair kernel, partial-sum update) and keep the fastest.  The
+// state is not advanced.
+ct_status autotune(ct_ctx *c)
+{
+    const int fp32 = c->p.precision == CT_FP32;
+    const TuneKey key{fp32, c->device, log2_bucket(c->shape.B), log2_bucket(c->shape.n_max),
+                      log2_bucket(c->shape.N)};
+    {
+        std::lock_guard<std::mutex> lk(g_tuned_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            ct::LaunchCfg best = it->second;
+            ct_status st = ensure_part(c, best, c->shape.N, c->shape.n_max);
+            if (st == CT_OK) st = ensure_work(c, best, c->shape.n);
+            if (st == CT_OK) c->cfg = best;
+            return st;
+        }
+    }
+    ct_status st = ensure_field_buf(c, c->shape.N);
+    if (st != CT_OK) return st;
+    std::vector<ct::LaunchCfg> cand;
+    for (int bs : {128, 256})
+        for (int chunk : {0, 512, 768, 1024, 2048, 4096}) {
+            if (chunk && (chunk % bs || chunk >= c->shape.n_max)) continue;
+            cand.push_back(ct::LaunchCfg{1, bs, chunk});
+        }
+    cand.push_back(ct::LaunchCfg{2, 128, 0});
+    ct::LaunchCfg best = c->cfg;
+    float best_ms = 1e30f;
+    for (const ct::LaunchCfg &cfg : cand) {
+        st = ensure_part(c, cfg, c->shape.N, c->shape.n_max);
+        if (st == CT_OK) st = ensure_work(c, cfg, c->shape.n);
+        if (st != CT_OK) return st;
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            CT_HIP(hipEventRecord(c->ev_a[0], c->stream));
+            CT_HIP(ct::launch_plan(c->bt, cfg, c->stream));
+            CT_HIP(ct::launch_step(c->dp, c->bt, cfg, fp32, c->grid, 1, c->field_buf, c->stream));
+            CT_HIP(ct::launch_update(c->dp, c->bt, cfg, c->shape.n_max, 1, c->field_buf, c->stream));
+            CT_HIP(hipEventRecord(c->ev_b[0], c->stream));
+            CT_HIP(hipEventSynchronize(c->ev_b[0]));
+            float ms = 0.0f;
+            CT_HIP(hipEventElapsedTime(&ms, c->ev_a[0], c->ev_b[0]));
+            if (rep > 0) ms_min = std::min(ms_min, ms);
+        }
+        if (ms_min < best_ms) {
+            best_ms = ms_min;
+            best = cfg;
+        }
+    }
+    st = ensure_part(c, best, c->shape.N, c->shape.n_max);
+    if (st == CT_OK) st = ensure_work(c, best, c->shape.n);
+    if (st != CT_OK) return st;
+    c->cfg = best;
+    // the field pass reset the drifting-hole total on the device: restore it
+    CT_HIP(hipMemcpyAsync(c->bt.active, &c->n_active, sizeof(int64_t), hipMemcpyHostToDevice,
+                          c->stream));
+    CT_HIP(hipStreamSynchronize(c->stream));
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    g_tuned[key] = best;
     return CT_OK;
 }
 
@@ -400,6 +584,7 @@ ct_status ct_init_sensor(const ct_sensor_params *p, ct_ctx **out)
     c->dp = make_dev_params(*p);
     c->device = dev;
     c->cfg = default_cfg(*p);
+    c->cu_count = prop.multiProcessorCount;
     auto bail = [&](ct_status s2) {
         ct_destroy(c);
         return s2;
@@ -448,6 +633,10 @@ ct_status ct_set_launch(ct_ctx *c, int32_t kt, int32_t bs, int32_t chunk)
         ct_status st = set_device(c);
         if (st != CT_OK) return st;
         st = ensure_part(c, n, c->shape.N, c->shape.n_max);
+        if (st != CT_OK) return st;
+        st = ensure_work(c, n, c->shape.n);
+        if (st != CT_OK) return st;
+        st = drop_graph(c);
         if (st != CT_OK) return st;
     }
     c->cfg = n;
@@ -498,8 +687,11 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     if (st != CT_OK) return st;
     st = ensure_part(c, c->cfg, s.N, s.n_max);
     if (st != CT_OK) return st;
+    st = ensure_work(c, c->cfg, s.n);
+    if (st != CT_OK) return st;
     void *w = c->ws;
-    ct::DevBatch bt{};
+    ct::DevBatch bt;
+    std::memset(&bt, 0, sizeof bt);  // compared bytewise against the captured graph
     bt.n_events = (int32_t)s.B;
     bt.n_total = (int32_t)s.N;
     bt.first_event_id = first_event_id;
@@ -521,7 +713,12 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     bt.out_cstep = at<int32_t>(w, L.out_cstep);
     bt.pix = at<int32_t>(w, L.pix);
     bt.pairs = at<uint64_t>(w, L.pairs);
-    bt.active2 = at<int64_t>(w, L.active2);
+    bt.active = at<int64_t>(w, L.active);
+    bt.item_base = at<int32_t>(w, L.item_base);
+    bt.n_items = at<int32_t>(w, L.n_items);
+    bt.counter = at<uint32_t>(w, L.counter);
+    bt.work = c->work_buf;
+    bt.work_cap = (int32_t)c->work_cap;
     bt.part = c->part_buf;
     bt.part_chunks = default_chunks(c->cfg.chunk, s.n_max);
     bt.sigma = at<double>(w, L.sigma);
@@ -546,7 +743,7 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     CT_HIP(up(bt.ref, ref.data(), sizeof(double) * 4 * s.B));
     CT_HIP(up((void *)bt.rngid, rngid.data(), sizeof(int32_t) * s.N));
     CT_HIP(up(bt.pairs, zeros64.data(), sizeof(uint64_t) * s.B));
-    CT_HIP(up(bt.active2, zeros64.data(), sizeof(int64_t) * 2));
+    CT_HIP(up(bt.active, zeros64.data(), sizeof(int64_t)));
     CT_HIP(up((void *)bt.sigma, sigma.data(), sizeof(double) * s.B));
     CT_HIP(up((void *)bt.dep_off, dep_off.data(), sizeof(int32_t) * (s.B + 1)));
     CT_HIP(up((void *)bt.deposits, deps.data(), sizeof(double) * deps.size()));
@@ -555,8 +752,7 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     CT_HIP(up((void *)bt.start, start.data(), sizeof(int64_t) * s.B));
     CT_HIP(ct::launch_fill_i32(bt.pix, s.B * G1, 0, sm));
     CT_HIP(ct::launch_seed(c->dp, bt, sm));
-    c->parity = 0;
-    CT_HIP(ct::launch_compact(c->dp, bt, 0, c->parity, sm));
+    CT_HIP(ct::launch_compact(c->dp, bt, 0, sm));
     c->bt = bt;
     c->L = L;
     c->shape = s;
@@ -566,9 +762,11 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     c->step_wall_ms = 0.0;
     st = sync_active(c);
     if (st != CT_OK) return st;
-    st = refresh_n_max(c);
-    if (st != CT_OK) return st;
     c->seeded = true;
+    if ((c->p.options & CT_OPT_AUTOTUNE) && (c->p.physics_flags & CT_REPULSION) && s.N > 0) {
+        st = autotune(c);
+        if (st != CT_OK) return st;
+    }
     return CT_OK;
 }
 
@@ -581,8 +779,7 @@ ct_status ct_step(ct_ctx *c, int64_t max_steps, int64_t *steps_done, int64_t *n_
     if (max_steps <= 0) max_steps = c->p.max_steps;
     const auto t_start = std::chrono::steady_clock::now();
     const bool timing = (c->p.options & CT_OPT_TIMING) != 0;
-    const int fp32 = c->p.precision == CT_FP32;
-    const int poll = 16;
+    const bool use_graph = !(c->p.options & CT_OPT_NO_GRAPH);
     std::vector<int64_t> taken0(c->shape.B), taken1(c->shape.B);
     if (c->shape.B > 0) {
         CT_HIP(hipMemcpyAsync(taken0.data(), c->bt.ev_taken, sizeof(int64_t) * c->shape.B,
@@ -593,15 +790,17 @@ ct_status ct_step(ct_ctx *c, int64_t max_steps, int64_t *steps_done, int64_t *n_
     if (!(c->p.physics_flags & CT_REPULSION)) cfg.chunk = 0;
     int64_t issued = 0;
     while (c->n_active > 0 && issued < max_steps) {
-        const int k = (int)std::min<int64_t>(poll, max_steps - issued);
-        const int32_t nm = c->n_max_live;
-        for (int i = 0; i < k; ++i) {
-            if (timing) CT_HIP(hipEventRecord(c->ev_a[i], c->stream));
-            CT_HIP(ct::launch_step(c->dp, c->bt, cfg, fp32, nm, 0, nullptr, c->stream));
-            if (timing) CT_HIP(hipEventRecord(c->ev_b[i], c->stream));
-            CT_HIP(ct::launch_update(c->dp, c->bt, cfg, nm, 0, nullptr, c->stream));
-            c->parity ^= 1;
-            CT_HIP(ct::launch_compact(c->dp, c->bt, 1, c->parity, c->stream));
+        // one chunk: kGraphSteps captured steps, or the remainder issued eagerly;
+        // steps after the last hole is collected find empty work lists
+        const int k = (int)std::min<int64_t>(kGraphSteps, max_steps - issued);
+        // HIP events recorded inside a graph replay carry no timestamps, so
+        // timed runs issue their steps eagerly
+        if (use_graph && !timing && k == kGraphSteps) {
+            st = ensure_graph(c, cfg);
+            if (st != CT_OK) return st;
+            CT_HIP(hipGraphLaunch(c->graph_exec, c->stream));
+        } else {
+            for (int i = 0; i < k; ++i) CT_HIP(issue_step(c, cfg, i, timing));
         }
         issued += k;
         c->steps += k;
@@ -615,8 +814,6 @@ ct_status ct_step(ct_ctx *c, int64_t max_steps, int64_t *steps_done, int64_t *n_
             }
             c->field_launches += k;
         }
-        st = refresh_n_max(c);
-        if (st != CT_OK) return st;
     }
     if (c->shape.B > 0) {
         CT_HIP(hipMemcpyAsync(taken1.data(), c->bt.ev_taken, sizeof(int64_t) * c->shape.B,
@@ -645,7 +842,7 @@ ct_status ct_collect(ct_ctx *c, int32_t *pixel_counts, double *xyz, int32_t *col
     const int64_t B = c->shape.B, N = c->shape.N;
     const int G1 = c->p.grid_n * c->p.grid_n + 1;
     hipStream_t sm = c->stream;
-    if (xyz) CT_HIP(ct::launch_scatter_alive(c->bt, c->n_max_live, sm));
+    if (xyz) CT_HIP(ct::launch_scatter_alive(c->bt, c->shape.n_max, sm));
     if (pixel_counts && B)
         CT_HIP(hipMemcpyAsync(pixel_counts, c->bt.pix, sizeof(int32_t) * B * G1,
                               hipMemcpyDeviceToHost, sm));
@@ -688,23 +885,16 @@ ct_status ct_field(ct_ctx *c, double *field)
     if (st != CT_OK) return st;
     const int64_t N = c->shape.N;
     if (N == 0) return CT_OK;
-    if (c->field_buf_n < (size_t)N) {
-        if (c->field_buf) CT_HIP(hipFree(c->field_buf));
-        c->field_buf = nullptr;
-        c->field_buf_n = 0;
-        if (hipMalloc((void **)&c->field_buf, sizeof(double) * 3 * N) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(CT_ENOMEM, "field buffer allocation failed");
-        }
-        c->field_buf_n = (size_t)N;
-    }
+    st = ensure_field_buf(c, N);
+    if (st != CT_OK) return st;
     // NaN everywhere, then the drifting carriers' fields
     CT_HIP(ct::launch_fill_i32((int32_t *)c->field_buf, 6 * N, (int32_t)0xFFFFFFFF, c->stream));
     ct::LaunchCfg cfg = c->cfg;
     if (!(c->p.physics_flags & CT_REPULSION)) cfg.chunk = 0;
     const int fp32 = c->p.precision == CT_FP32;
-    CT_HIP(ct::launch_step(c->dp, c->bt, cfg, fp32, c->n_max_live, 1, c->field_buf, c->stream));
-    CT_HIP(ct::launch_update(c->dp, c->bt, cfg, c->n_max_live, 1, c->field_buf, c->stream));
+    CT_HIP(ct::launch_plan(c->bt, cfg, c->stream));
+    CT_HIP(ct::launch_step(c->dp, c->bt, cfg, fp32, c->grid, 1, c->field_buf, c->stream));
+    CT_HIP(ct::launch_update(c->dp, c->bt, cfg, c->shape.n_max, 1, c->field_buf, c->stream));
     CT_HIP(hipMemcpyAsync(field, c->field_buf, sizeof(double) * 3 * N, hipMemcpyDeviceToHost,
                           c->stream));
     CT_HIP(hipStreamSynchronize(c->stream));
@@ -752,6 +942,9 @@ void ct_destroy(ct_ctx *c)
     if (c->ws && !c->ws_bound) (void)hipFree(c->ws);
     if (c->field_buf) (void)hipFree(c->field_buf);
     if (c->part_buf) (void)hipFree(c->part_buf);
+    if (c->work_buf) (void)hipFree(c->work_buf);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     for (int i = 0; i < 64; ++i) {
         if (c->ev_a[i]) (void)hipEventDestroy(c->ev_a[i]);

@@ -27,6 +27,12 @@ struct DevParams {
 // Device view of one batch.  Slots [off[b], off[b] + n_act[b]) of the
 // position arrays hold the drifting holes of event b, compacted and in
 // carrier order.
+// One work item of the step kernel: the target tile `tile` of event b
+// against its source chunk c of nsplit.
+struct Item {
+    int32_t b, tile, c, nsplit;
+};
+
 struct DevBatch {
     int32_t n_events;
     int32_t n_total;
@@ -44,9 +50,14 @@ struct DevBatch {
     int32_t *out_cstep;     // [N] by carrier
     int32_t *pix;           // [B][grid_n^2 + 1]
     uint64_t *pairs;        // [B]
-    int64_t *active2;       // [2] parity slots of the drifting-hole total
+    int64_t *active;        // [1] drifting holes after the last compaction
     double *part;           // [nsplit][3][N] partial fields of split events
     int32_t part_chunks;    // chunks the partial buffer holds
+    Item *work;             // [work_cap] work list of the current step
+    int32_t work_cap;
+    int32_t *item_base;     // [B] first item of each event
+    int32_t *n_items;       // [1]
+    uint32_t *counter;      // [1] next item to take
     // seeding inputs
     const double *sigma;    // [B]
     const int32_t *dep_off; // [B + 1]
@@ -59,15 +70,17 @@ struct DevBatch {
 struct LaunchCfg {
     int kt;        // targets per thread
     int bs;        // block size
-    int chunk;     // sources per workgroup chunk; events with more are split
+    int chunk;     // longest source chunk of one work item; an event with n holes is
+                   // split into ceil(n / chunk) chunks of equal length (0: no split)
 };
 
 // Kernel launchers (ct_kernels.hip).  All return the launch status.
 hipError_t launch_seed(const DevParams &dp, const DevBatch &bt, hipStream_t s);
-hipError_t launch_compact(const DevParams &dp, const DevBatch &bt, int count_step, int parity,
-                          hipStream_t s);
+hipError_t launch_compact(const DevParams &dp, const DevBatch &bt, int count_step, hipStream_t s);
+hipError_t launch_plan(const DevBatch &bt, const LaunchCfg &cfg, hipStream_t s);
 hipError_t launch_step(const DevParams &dp, const DevBatch &bt, const LaunchCfg &cfg, int fp32,
-                       int n_max, int field_only, double *field_out, hipStream_t s);
+                       int grid, int field_only, double *field_out, hipStream_t s);
+int step_occupancy(const LaunchCfg &cfg, int fp32);
 bool launch_supported(int kt, int bs);
 hipError_t launch_update(const DevParams &dp, const DevBatch &bt, const LaunchCfg &cfg, int n_max,
                          int field_only, double *field_out, hipStream_t s);

@@ -205,63 +205,105 @@ __device__ __forceinline__ void pair_f64(const D4 &s, double s2, const double (&
 
 // ------------------------------------------------------------------ kernels
 
-// Grid: (target tiles, events, source chunks).  A workgroup owns BS*KT
-// targets (thread t, target m -> slot tile*BS*KT + m*BS + t) and walks the
-// sources [sb, se) of its chunk in LDS tiles of BS.
-template <int KT, int BS>
-__global__ __launch_bounds__(BS) void k_step_f32(DevParams dp, DevBatch bt, int chunk,
-                                                 int field_only, double *field_out)
+// Sources of an event split into nsplit chunks: equal lengths rounded up to
+// whole LDS tiles, so every chunk boundary is also a tile boundary.
+__device__ __forceinline__ int chunk_length(int n, int nsplit, int bs)
 {
-    const int b = blockIdx.y;
+    if (nsplit <= 1) return n;
+    const int per = (n + nsplit - 1) / nsplit;
+    return (per + bs - 1) / bs * bs;
+}
+
+// Pair work of one item.  Thread t owns targets tile*BS*KT + m*BS + t
+// (m < KT); the workgroup stages the sources in LDS tiles of BS.  Waves whose
+// targets all lie past the event's end only help staging.  For unsplit events
+// the update follows in the same kernel; otherwise the raw partial sum is
+// stored for k_update.
+template <int KT, int BS, bool F32>
+__device__ void run_item(const DevParams &dp, const DevBatch &bt, const Item it, int chunk,
+                         int field_only, double *field_out, void *lds)
+{
+    const int b = it.b;
     const int n = bt.n_act[b];
-    const int t0 = blockIdx.x * (BS * KT);
-    if (t0 >= n) return;
-    const int nsplit = chunk > 0 ? (n + chunk - 1) / chunk : 1;
-    const int c = blockIdx.z;
-    if (c >= nsplit) return;
-    const int sb = chunk > 0 ? c * chunk : 0;
-    const int se = chunk > 0 ? min(n, sb + chunk) : n;
+    const int t0 = it.tile * (BS * KT);
+    const int clen = chunk_length(n, it.nsplit, BS);
+    const int sb = it.c * clen;
+    const int se = min(n, sb + clen);
     const int base = bt.off[b];
     const int tid = threadIdx.x;
+    const bool wave_has_targets = t0 + (tid & ~63) < n;
 
     double ex[KT], ey[KT], ez[KT];
 #pragma unroll
     for (int m = 0; m < KT; ++m) ex[m] = ey[m] = ez[m] = 0.0;
 
     if (dp.flags & 1u) {
-        __shared__ float4 tile[BS];
-        const double rx = bt.ref[4 * b + 0], ry = bt.ref[4 * b + 1], rz = bt.ref[4 * b + 2];
-        float tx[KT], ty[KT], tz[KT];
+        if constexpr (F32) {
+            float4 *tile = static_cast<float4 *>(lds);
+            const double rx = bt.ref[4 * b + 0], ry = bt.ref[4 * b + 1], rz = bt.ref[4 * b + 2];
+            float tx[KT], ty[KT], tz[KT];
 #pragma unroll
-        for (int m = 0; m < KT; ++m) {
-            const int s = t0 + m * BS + tid;
-            if (s < n) {
-                tx[m] = (float)(bt.cx[base + s] - rx);
-                ty[m] = (float)(bt.cy[base + s] - ry);
-                tz[m] = (float)(bt.cz[base + s] - rz);
-            } else {
-                tx[m] = ty[m] = tz[m] = 0.0f;
+            for (int m = 0; m < KT; ++m) {
+                const int s = t0 + m * BS + tid;
+                if (s < n) {
+                    tx[m] = (float)(bt.cx[base + s] - rx);
+                    ty[m] = (float)(bt.cy[base + s] - ry);
+                    tz[m] = (float)(bt.cz[base + s] - rz);
+                } else {
+                    tx[m] = ty[m] = tz[m] = 0.0f;
+                }
             }
-        }
-        for (int s0 = sb; s0 < se; s0 += BS) {
-            __syncthreads();
-            const int j = s0 + tid;
-            float4 v = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
-            if (j < se)
-                v = make_float4((float)(bt.cx[base + j] - rx), (float)(bt.cy[base + j] - ry),
-                                (float)(bt.cz[base + j] - rz), 0.0f);
-            tile[tid] = v;
-            __syncthreads();
-            const int cnt = (min(BS, se - s0) + 7) & ~7;
-            float ax[KT], ay[KT], az[KT];
+            for (int s0 = sb; s0 < se; s0 += BS) {
+                __syncthreads();
+                const int j = s0 + tid;
+                float4 v = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
+                if (j < se)
+                    v = make_float4((float)(bt.cx[base + j] - rx), (float)(bt.cy[base + j] - ry),
+                                    (float)(bt.cz[base + j] - rz), 0.0f);
+                tile[tid] = v;
+                __syncthreads();
+                if (!wave_has_targets) continue;
+                const int cnt = (min(BS, se - s0) + 7) & ~7;
+                float ax[KT], ay[KT], az[KT];
 #pragma unroll
-            for (int m = 0; m < KT; ++m) ax[m] = ay[m] = az[m] = 0.0f;
-            pairs_f32<KT>(tile, cnt, dp.s2f, tx, ty, tz, ax, ay, az);
+                for (int m = 0; m < KT; ++m) ax[m] = ay[m] = az[m] = 0.0f;
+                pairs_f32<KT>(tile, cnt, dp.s2f, tx, ty, tz, ax, ay, az);
 #pragma unroll
-            for (int m = 0; m < KT; ++m) {  // fold the tile's FP32 partial into FP64
-                ex[m] += (double)ax[m];
-                ey[m] += (double)ay[m];
-                ez[m] += (double)az[m];
+                for (int m = 0; m < KT; ++m) {  // fold the tile's FP32 partial into FP64
+                    ex[m] += (double)ax[m];
+                    ey[m] += (double)ay[m];
+                    ez[m] += (double)az[m];
+                }
+            }
+        } else {
+            D4 *tile = static_cast<D4 *>(lds);
+            double tx[KT], ty[KT], tz[KT];
+#pragma unroll
+            for (int m = 0; m < KT; ++m) {
+                const int s = t0 + m * BS + tid;
+                if (s < n) {
+                    tx[m] = bt.cx[base + s];
+                    ty[m] = bt.cy[base + s];
+                    tz[m] = bt.cz[base + s];
+                } else {
+                    tx[m] = ty[m] = tz[m] = 0.0;
+                }
+            }
+            const double s2 = dp.s2;
+            for (int s0 = sb; s0 < se; s0 += BS) {
+                __syncthreads();
+                const int j = s0 + tid;
+                if (j < se) tile[tid] = D4{bt.cx[base + j], bt.cy[base + j], bt.cz[base + j], 0.0};
+                __syncthreads();
+                if (!wave_has_targets) continue;
+                const int cnt = min(BS, se - s0);
+                const int cnt4 = cnt & ~3;
+                for (int j0 = 0; j0 < cnt4; j0 += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        pair_f64<KT>(tile[j0 + u], s2, tx, ty, tz, ex, ey, ez);
+                }
+                for (int jj = cnt4; jj < cnt; ++jj) pair_f64<KT>(tile[jj], s2, tx, ty, tz, ex, ey, ez);
             }
         }
     }
@@ -269,80 +311,88 @@ __global__ __launch_bounds__(BS) void k_step_f32(DevParams dp, DevBatch bt, int 
     for (int m = 0; m < KT; ++m) {
         const int s = t0 + m * BS + tid;
         if (s >= n) continue;
-        if (nsplit == 1) {
+        if (it.nsplit == 1) {
             field_or_advance(dp, bt, b, base + s, dp.K * ex[m], dp.K * ey[m], dp.K * ez[m],
                              field_only, field_out);
         } else {
             const int64_t N = bt.n_total;
-            bt.part[(3 * (int64_t)c + 0) * N + base + s] = ex[m];
-            bt.part[(3 * (int64_t)c + 1) * N + base + s] = ey[m];
-            bt.part[(3 * (int64_t)c + 2) * N + base + s] = ez[m];
+            bt.part[(3 * (int64_t)it.c + 0) * N + base + s] = ex[m];
+            bt.part[(3 * (int64_t)it.c + 1) * N + base + s] = ey[m];
+            bt.part[(3 * (int64_t)it.c + 2) * N + base + s] = ez[m];
         }
     }
 }
 
-template <int KT, int BS>
-__global__ __launch_bounds__(BS) void k_step_f64(DevParams dp, DevBatch bt, int chunk,
-                                                 int field_only, double *field_out)
+// Persistent step kernel: a fixed grid sized to the resident capacity of the
+// device; each workgroup takes the next item of the step's work list with one
+// atomic until the list is exhausted, so every workgroup exits.
+template <int KT, int BS, bool F32>
+__global__ __launch_bounds__(BS) void k_step(DevParams dp, DevBatch bt, int chunk, int field_only,
+                                             double *field_out)
 {
-    const int b = blockIdx.y;
-    const int n = bt.n_act[b];
-    const int t0 = blockIdx.x * (BS * KT);
-    if (t0 >= n) return;
-    const int nsplit = chunk > 0 ? (n + chunk - 1) / chunk : 1;
-    const int c = blockIdx.z;
-    if (c >= nsplit) return;
-    const int sb = chunk > 0 ? c * chunk : 0;
-    const int se = chunk > 0 ? min(n, sb + chunk) : n;
-    const int base = bt.off[b];
-    const int tid = threadIdx.x;
-
-    double ex[KT], ey[KT], ez[KT];
-#pragma unroll
-    for (int m = 0; m < KT; ++m) ex[m] = ey[m] = ez[m] = 0.0;
-
-    if (dp.flags & 1u) {
-        __shared__ D4 tile[BS];
-        double tx[KT], ty[KT], tz[KT];
-#pragma unroll
-        for (int m = 0; m < KT; ++m) {
-            const int s = t0 + m * BS + tid;
-            if (s < n) {
-                tx[m] = bt.cx[base + s];
-                ty[m] = bt.cy[base + s];
-                tz[m] = bt.cz[base + s];
-            } else {
-                tx[m] = ty[m] = tz[m] = 0.0;
-            }
-        }
-        const double s2 = dp.s2;
-        for (int s0 = sb; s0 < se; s0 += BS) {
-            __syncthreads();
-            const int j = s0 + tid;
-            if (j < se) tile[tid] = D4{bt.cx[base + j], bt.cy[base + j], bt.cz[base + j], 0.0};
-            __syncthreads();
-            const int cnt = min(BS, se - s0);
-            const int cnt4 = cnt & ~3;
-            for (int j0 = 0; j0 < cnt4; j0 += 4) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) pair_f64<KT>(tile[j0 + u], s2, tx, ty, tz, ex, ey, ez);
-            }
-            for (int jj = cnt4; jj < cnt; ++jj) pair_f64<KT>(tile[jj], s2, tx, ty, tz, ex, ey, ez);
-        }
+    __shared__ int s_item;
+    __shared__ __attribute__((aligned(32))) char lds[BS * (F32 ? sizeof(float4) : sizeof(D4))];
+    const int n_items = *bt.n_items;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(bt.counter, 1u);
+        __syncthreads();
+        const int i = s_item;
+        if (i >= n_items) break;
+        run_item<KT, BS, F32>(dp, bt, bt.work[i], chunk, field_only, field_out, lds);
     }
-#pragma unroll
-    for (int m = 0; m < KT; ++m) {
-        const int s = t0 + m * BS + tid;
-        if (s >= n) continue;
-        if (nsplit == 1) {
-            field_or_advance(dp, bt, b, base + s, dp.K * ex[m], dp.K * ey[m], dp.K * ez[m],
-                             field_only, field_out);
-        } else {
-            const int64_t N = bt.n_total;
-            bt.part[(3 * (int64_t)c + 0) * N + base + s] = ex[m];
-            bt.part[(3 * (int64_t)c + 1) * N + base + s] = ey[m];
-            bt.part[(3 * (int64_t)c + 2) * N + base + s] = ez[m];
+}
+
+// Work list of one step (one workgroup of 1024): per event ceil(n/T) target
+// tiles times ceil(n/chunk) source chunks, events in order, items of an event
+// contiguous.  Also resets the item counter and the drifting-hole total.
+__global__ __launch_bounds__(1024) void k_plan(DevBatch bt, int T, int chunk)
+{
+    __shared__ int wtot[16];
+    __shared__ int carry;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int B = bt.n_events;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int e0 = 0; e0 < B; e0 += 1024) {
+        const int e = e0 + tid;
+        int items = 0;
+        if (e < B) {
+            const int n = bt.n_act[e];
+            if (n > 0) items = ((n + T - 1) / T) * (chunk > 0 ? (n + chunk - 1) / chunk : 1);
         }
+        int v = items;  // inclusive scan within the wave
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(v, o);
+            if (lane >= o) v += t;
+        }
+        if (lane == 63) wtot[wave] = v;
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            before += q < wave ? wtot[q] : 0;
+            total += wtot[q];
+        }
+        if (e < B) bt.item_base[e] = carry + before + v - items;
+        __syncthreads();
+        if (tid == 0) carry += total;
+        __syncthreads();
+    }
+    const int total = min(carry, bt.work_cap);
+    for (int e = wave; e < B; e += 16) {
+        const int n = bt.n_act[e];
+        if (n <= 0) continue;
+        const int ns = chunk > 0 ? (n + chunk - 1) / chunk : 1;
+        const int items = ((n + T - 1) / T) * ns;
+        const int base = bt.item_base[e];
+        for (int i = lane; i < items; i += 64)
+            if (base + i < bt.work_cap) bt.work[base + i] = Item{e, i / ns, i % ns, ns};
+    }
+    if (tid == 0) {
+        *bt.n_items = total;
+        *bt.counter = 0u;
+        bt.active[0] = 0;
     }
 }
 
@@ -374,7 +424,7 @@ __global__ __launch_bounds__(256) void k_update(DevParams dp, DevBatch bt, int c
 // wave totals; carrier indices are compacted in place (every read of a chunk
 // precedes the barrier, every write follows it and lands at or below it).
 __global__ __launch_bounds__(kCompactThreads) void k_compact(DevParams dp, DevBatch bt,
-                                                             int count_step, int parity)
+                                                             int count_step)
 {
     (void)dp;
     constexpr int W = kCompactThreads / 64;
@@ -456,8 +506,7 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(DevParams dp, DevBa
             bt.ev_step[b] += 1;
             bt.ev_taken[b] += 1;
         }
-        if (kept > 0) atomicAdd((unsigned long long *)&bt.active2[parity], (unsigned long long)kept);
-        if (b == 0) bt.active2[parity ^ 1] = 0;
+        if (kept > 0) atomicAdd((unsigned long long *)bt.active, (unsigned long long)kept);
     }
 }
 
@@ -544,18 +593,26 @@ __global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int64_t n, int32_t
 
 template <int KT, int BS>
 hipError_t launch_step_t(const DevParams &dp, const DevBatch &bt, const LaunchCfg &cfg, int fp32,
-                         int n_max, int field_only, double *field_out, hipStream_t s)
+                         int grid, int field_only, double *field_out, hipStream_t s)
 {
-    const int tiles = (n_max + BS * KT - 1) / (BS * KT);
-    const int splits = cfg.chunk > 0 ? (n_max + cfg.chunk - 1) / cfg.chunk : 1;
-    const dim3 grid(tiles, bt.n_events, splits);
     if (fp32)
-        hipLaunchKernelGGL((k_step_f32<KT, BS>), grid, dim3(BS), 0, s, dp, bt, cfg.chunk, field_only,
-                           field_out);
+        hipLaunchKernelGGL((k_step<KT, BS, true>), dim3(grid), dim3(BS), 0, s, dp, bt, cfg.chunk,
+                           field_only, field_out);
     else
-        hipLaunchKernelGGL((k_step_f64<KT, BS>), grid, dim3(BS), 0, s, dp, bt, cfg.chunk, field_only,
-                           field_out);
+        hipLaunchKernelGGL((k_step<KT, BS, false>), dim3(grid), dim3(BS), 0, s, dp, bt, cfg.chunk,
+                           field_only, field_out);
     return hipGetLastError();
+}
+
+template <int KT, int BS>
+int occupancy_t(int fp32)
+{
+    int nb = 0;
+    hipError_t e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &nb, reinterpret_cast<const void *>(&k_step<KT, BS, true>), BS, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &nb, reinterpret_cast<const void *>(&k_step<KT, BS, false>), BS, 0);
+    return e == hipSuccess ? nb : -1;
 }
 
 }  // namespace
@@ -569,36 +626,50 @@ hipError_t launch_seed(const DevParams &dp, const DevBatch &bt, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const DevParams &dp, const DevBatch &bt, int count_step, int parity,
-                          hipStream_t s)
+hipError_t launch_compact(const DevParams &dp, const DevBatch &bt, int count_step, hipStream_t s)
 {
     if (bt.n_events <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_compact, dim3(bt.n_events), dim3(kCompactThreads), 0, s, dp, bt,
-                       count_step, parity);
+                       count_step);
     return hipGetLastError();
 }
 
-// field_out receives the field ([N][3], carrier order) when field_only is set.
-hipError_t launch_step(const DevParams &dp, const DevBatch &bt, const LaunchCfg &cfg, int fp32,
-                       int n_max, int field_only, double *field_out, hipStream_t s)
+hipError_t launch_plan(const DevBatch &bt, const LaunchCfg &cfg, hipStream_t s)
 {
-    if (bt.n_events <= 0 || n_max <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, bt, cfg.bs * cfg.kt, cfg.chunk);
+    return hipGetLastError();
+}
+
+#define CT_LAUNCH_CASES(X) \
+    X(1, 64) X(2, 64) X(4, 64) X(1, 128) X(2, 128) X(4, 128) X(1, 256) X(2, 256) X(4, 256)
+
+// Persistent step launch over the work list built by launch_plan; field_out
+// receives the field ([N][3], carrier order) when field_only is set.
+hipError_t launch_step(const DevParams &dp, const DevBatch &bt, const LaunchCfg &cfg, int fp32,
+                       int grid, int field_only, double *field_out, hipStream_t s)
+{
+    if (bt.n_events <= 0 || grid <= 0) return hipSuccess;
 #define CT_STEP_CASE(KT_, BS_) \
     if (cfg.kt == KT_ && cfg.bs == BS_) \
-        return launch_step_t<KT_, BS_>(dp, bt, cfg, fp32, n_max, field_only, field_out, s);
-    CT_STEP_CASE(1, 128)
-    CT_STEP_CASE(2, 128)
-    CT_STEP_CASE(4, 128)
-    CT_STEP_CASE(1, 256)
-    CT_STEP_CASE(2, 256)
-    CT_STEP_CASE(4, 256)
+        return launch_step_t<KT_, BS_>(dp, bt, cfg, fp32, grid, field_only, field_out, s);
+    CT_LAUNCH_CASES(CT_STEP_CASE)
 #undef CT_STEP_CASE
     return hipErrorInvalidValue;
 }
 
+// Resident workgroups per compute unit of the step kernel for a configuration.
+int step_occupancy(const LaunchCfg &cfg, int fp32)
+{
+#define CT_OCC_CASE(KT_, BS_) \
+    if (cfg.kt == KT_ && cfg.bs == BS_) return occupancy_t<KT_, BS_>(fp32);
+    CT_LAUNCH_CASES(CT_OCC_CASE)
+#undef CT_OCC_CASE
+    return -1;
+}
+
 bool launch_supported(int kt, int bs)
 {
-    return (kt == 1 || kt == 2 || kt == 4) && (bs == 128 || bs == 256);
+    return (kt == 1 || kt == 2 || kt == 4) && (bs == 64 || bs == 128 || bs == 256);
 }
 
 hipError_t launch_update(const DevParams &dp, const DevBatch &bt, const LaunchCfg &cfg, int n_max,

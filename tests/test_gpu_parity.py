@@ -396,3 +396,37 @@ def test_error_paths(ct):
         sim.seed(explicit_batch([np.zeros((0, 3)), [[0, 0, -1.0]]]))
         r = sim.collect()
         assert r["pix"][1].sum() == 1 and r["pix"][0].sum() == 0
+
+
+def test_graph_equals_eager_bitwise(ct):
+    """The captured step loop, eager launches and the timed variant give the
+    same bits; the timed variant reports the step-kernel time."""
+    s, b = batch_8kev(n_events=8, seed=6)
+    for prec in (FP64, FP32):
+        g = gpu_run(ct, s, b, prec)
+        with ct.Simulator(s, prec, options=ct.CT_OPT_NO_GRAPH) as sim:
+            e = sim.run(b)
+        with ct.Simulator(s, prec, options=ct.CT_OPT_TIMING) as sim:
+            t = sim.run(b)
+        for r in (e, t):
+            np.testing.assert_array_equal(g["xyz"], r["xyz"])
+            np.testing.assert_array_equal(g["cstep"], r["cstep"])
+            np.testing.assert_array_equal(g["pix"], r["pix"])
+        assert t["stats"].field_launches >= t["steps"].max() and t["stats"].field_kernel_ms > 0
+
+
+def test_autotuned_launch_matches_oracle(ct):
+    """The autotuner only changes the launch shape: sampled events still meet
+    both tolerances, and the chosen configuration is reported."""
+    s, b = batch_8kev(n_events=64, seed=8)
+    for prec in (FP64, FP32):
+        with ct.Simulator(s, prec, options=ct.CT_OPT_AUTOTUNE) as sim:
+            g = sim.run(b)
+        st = g["stats"]
+        assert st.block_size in (128, 256) and st.targets_per_thread in (1, 2)
+        for e in (0, 31, 63):
+            o = oracle.run(s, b.event(e))
+            if prec == FP64:
+                assert_fp64_parity(_event_slice(g, e), o, f"autotuned event {e}")
+            else:
+                assert_fp32_parity(_event_slice(g, e), o, f"autotuned event {e}")
