@@ -41,7 +41,39 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--launch", default="", help="kt,bs,chunk override")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library time launch shapes on the seeded state")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first copy this many MiB device-to-device with torch (a reference "
+                         "kernel of known traffic for hardware byte counters)")
     return ap.parse_args()
+
+
+# Algorithmic HBM bytes of one hole update in the step kernel: the target's
+# FP64 position (24 B) and carrier index (4 B) read, its RNG id (4 B) read,
+# the new FP64 position (24 B) written.  Sources are re-read from cache.
+ALG_BYTES_PER_HOLE_STEP = 56
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_step_f32_batch_8kev_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2506_09712_amd", "csrc", "ct_kernels.hip")
+
+
+def measured_traffic(hole_steps_per_launch):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary (bytes per hole update), or None when the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None, "no counter summary"
+    vals = dict(line.split(":", 1) for line in text.splitlines()
+                if line.startswith(("bytes_per_hole_step:", "kernel_source_sha256:")))
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256", "").strip() != sha:
+        return None, "kernel changed since the counters were taken"
+    per = float(vals["bytes_per_hole_step"])
+    return per * hole_steps_per_launch, ("FETCH_SIZE and WRITE_SIZE per hole update, scaled by a "
+                                         "1 GiB copy; " + os.path.basename(TRAFFIC_PROFILE))
 
 
 def simulate(ct, sim, batch):
@@ -72,19 +104,29 @@ def main():
 
     print(f"bench: {a.workload} {batch.n_events} events, {int(batch.n_carriers.sum())} holes; "
           f"warmup {a.warmup}, steps {a.steps}", file=sys.stderr, flush=True)
+    if a.copy_calibration_mb:
+        n = a.copy_calibration_mb << 20
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"bench: calibration copy of {a.copy_calibration_mb} MiB done", file=sys.stderr,
+              flush=True)
+        del src, dst
 
-    tune = 0 if launch else ct.CT_OPT_AUTOTUNE
+    tune = ct.CT_OPT_AUTOTUNE if (a.autotune and not launch) else 0
 
     def timed_runs(options, label):
         sim = ct.Simulator(sensor, ct.CT_FP32, device=0, options=options | tune, launch=launch)
         for _ in range(a.warmup):
             simulate(ct, sim, batch)
         torch.cuda.synchronize()
-        pairs, kern_ms, launches = 0, 0.0, 0
+        pairs, kern_ms, launches, hsteps = 0, 0.0, 0, 0
         t0 = time.perf_counter()
         for _ in range(a.steps):
             r = simulate(ct, sim, batch)
             pairs += r["pairs"]
+            hsteps += r["hole_steps"]
             kern_ms += r["stats"].field_kernel_ms
             launches += r["stats"].field_launches
         torch.cuda.synchronize()
@@ -93,14 +135,16 @@ def main():
         sim.close()
         print(f"bench: {label}: {pairs / wall:.3e} pairs/s, {batch.n_events * a.steps / wall:.1f} "
               f"events/s", file=sys.stderr, flush=True)
-        return pairs, wall, kern_ms, launches, st
+        return pairs, wall, kern_ms, launches, st, hsteps
 
     # production path: captured step loop, all events in one launch per step
-    pairs, wall, _, _, st = timed_runs(0, "fp32-batched (graph)")
+    pairs, wall, _, _, st, _ = timed_runs(0, "fp32-batched (graph)")
     value = pairs / wall
     events_per_s = batch.n_events * a.steps / wall
     # same runs with HIP events around every step-kernel launch (eager issue)
-    tpairs, twall, kern_ms, launches, _ = timed_runs(ct.CT_OPT_TIMING, "fp32-batched (eager, timed)")
+    tpairs, twall, kern_ms, launches, _, thsteps = timed_runs(ct.CT_OPT_TIMING,
+                                                              "fp32-batched (eager, timed)")
+    traffic, traffic_note = measured_traffic(thsteps / max(launches, 1))
     achieved = FLOP_PER_PAIR * tpairs / (kern_ms * 1e-3) if kern_ms > 0 else None
     print(f"bench: step kernel {kern_ms / max(launches, 1):.3f} ms avg over {launches} launches, "
           f"{achieved / 1e12 if achieved else 0:.1f} TFLOP/s", file=sys.stderr, flush=True)
@@ -120,9 +164,13 @@ def main():
                               "block": st.block_size, "chunk_len": st.chunk_len}},
         "events_per_s": events_per_s,
         "pairs_per_run": pairs // a.steps,
+        "hole_steps_per_run": thsteps // a.steps,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12 if achieved else None,
                      "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VECTOR_PEAK if achieved else None, "traffic": None,
+                     "frac": achieved / FP32_VECTOR_PEAK if achieved else None,
+                     "traffic": traffic, "traffic_note": traffic_note,
+                     "algorithmic_bytes_per_launch": ALG_BYTES_PER_HOLE_STEP * thsteps / max(launches, 1),
+                     "hole_steps_per_launch": thsteps / max(launches, 1),
                      "kernel": "k_step<1,256,fp32>", "avg_launch_ms": kern_ms / max(launches, 1),
                      "launches": launches, "flop_per_pair": FLOP_PER_PAIR,
                      "timed_pass": {"value": tpairs / twall, "note": "same runs issued eagerly "

@@ -132,8 +132,9 @@ typedef struct {
     double step_wall_ms;       /* host wall time spent inside ct_step */
     int32_t targets_per_thread;/* launch configuration in use */
     int32_t block_size;
-    int32_t chunk_len;         /* sources per workgroup chunk (events above it are split) */
+    int32_t chunk_len;         /* longest source chunk of a work item (0 = events not split) */
     int32_t reserved;
+    uint64_t hole_steps;       /* sum over steps and events of N_a (hole updates performed) */
 } ct_run_stats;
 
 /* Create a context for one sensor configuration on one gfx950 device.

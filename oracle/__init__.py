@@ -84,7 +84,8 @@ def lib():
         L.oc_pixel_bin.argtypes = [C.POINTER(OcParams), C.c_double, C.c_double]
         L.oc_pixel_bin.restype = C.c_int32
         L.oc_run.argtypes = [C.POINTER(OcParams), C.POINTER(OcEvent), C.c_int32, C.c_uint64,
-                             ip, dp, ip, C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]
+                             ip, dp, ip, C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
+                             C.POINTER(C.c_uint64)]
         L.oc_run.restype = C.c_int
         L.oc_set_threads.argtypes = [C.c_int]
         L.oc_get_threads.restype = C.c_int
@@ -219,10 +220,10 @@ def run(sensor, batch, threads: Optional[int] = None) -> dict:
     xyz = np.zeros((int(off[-1]), 3), dtype=np.float64)
     cstep = np.zeros(int(off[-1]), dtype=np.int32)
     steps = np.zeros(batch.n_events, dtype=np.int64)
-    pairs = C.c_uint64(0)
+    pairs, hsteps = C.c_uint64(0), C.c_uint64(0)
     st = lib().oc_run(C.byref(p), evs, batch.n_events, batch.first_event_id,
                       pix.ctypes.data_as(C.POINTER(C.c_int32)), _dp(xyz),
                       cstep.ctypes.data_as(C.POINTER(C.c_int32)),
-                      steps.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(pairs))
+                      steps.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(pairs), C.byref(hsteps))
     return {"status": int(st), "pix": pix, "xyz": xyz, "cstep": cstep, "steps": steps,
-            "pairs": int(pairs.value), "offsets": off, "n": n}
+            "pairs": int(pairs.value), "hole_steps": int(hsteps.value), "offsets": off, "n": n}

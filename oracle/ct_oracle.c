@@ -297,7 +297,7 @@ static void retire(const oc_params *p, oc_work *w, int32_t i, int64_t step, int3
  * the carrier's position in the event. */
 static int run_event(const oc_params *p, const oc_event *ev, uint64_t eid, int parallel_targets,
                      int32_t *pix, double *xyz_out, int32_t *cstep, int64_t *steps_out,
-                     uint64_t *pairs_out)
+                     uint64_t *pairs_out, uint64_t *hole_steps_out)
 {
     const int32_t n = oc_carrier_count(p, ev);
     const double H = p->thickness_um;
@@ -308,6 +308,7 @@ static int run_event(const oc_params *p, const oc_event *ev, uint64_t eid, int p
     for (int32_t g = 0; g <= p->grid_n * p->grid_n; ++g) pix[g] = 0;
     *steps_out = 0;
     *pairs_out = 0;
+    *hole_steps_out = 0;
     if (n <= 0) return OC_OK;
 
     oc_work w;
@@ -368,6 +369,7 @@ static int run_event(const oc_params *p, const oc_event *ev, uint64_t eid, int p
             break;
         }
         *pairs_out += (uint64_t)na * (uint64_t)(na - 1);
+        *hole_steps_out += (uint64_t)na;
 #pragma omp parallel for schedule(static) if (parallel_targets)
         for (int64_t a = 0; a < na; ++a) {
             const int64_t i = w.act[a];
@@ -414,10 +416,11 @@ done:
 
 /* Run a batch.  Event b uses RNG event id first_event_id + b.  Outputs:
  * pix [B][grid_n^2 + 1], xyz_out [sum N_e][3], cstep [sum N_e] (-1 = alive),
- * steps [B], pairs = sum over steps of N_a (N_a - 1).  Returns the worst
- * status over events. */
+ * steps [B], pairs = sum over steps of N_a (N_a - 1), hole_steps = sum over
+ * steps of N_a.  Returns the worst status over events. */
 int oc_run(const oc_params *p, const oc_event *ev, int32_t n_events, uint64_t first_event_id,
-           int32_t *pix, double *xyz_out, int32_t *cstep, int64_t *steps, uint64_t *pairs)
+           int32_t *pix, double *xyz_out, int32_t *cstep, int64_t *steps, uint64_t *pairs,
+           uint64_t *hole_steps)
 {
     int st = check_params(p);
     if (st != OC_OK) return st;
@@ -439,14 +442,15 @@ int oc_run(const oc_params *p, const oc_event *ev, int32_t n_events, uint64_t fi
 #endif
     const int outer = n_events >= 2 * nthreads;
     const int G1 = p->grid_n * p->grid_n + 1;
-    uint64_t total_pairs = 0;
+    uint64_t total_pairs = 0, total_hs = 0;
     int worst = OC_OK;
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : total_pairs) if (outer)
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : total_pairs, total_hs) if (outer)
     for (int32_t b = 0; b < n_events; ++b) {
-        uint64_t pr = 0;
+        uint64_t pr = 0, hs = 0;
         const int s = run_event(p, &ev[b], first_event_id + (uint64_t)b, !outer, pix + (size_t)b * G1,
-                                xyz_out + 3 * off[b], cstep + off[b], steps + b, &pr);
+                                xyz_out + 3 * off[b], cstep + off[b], steps + b, &pr, &hs);
         total_pairs += pr;
+        total_hs += hs;
         if (s != OC_OK) {
 #pragma omp critical
             {
@@ -455,6 +459,7 @@ int oc_run(const oc_params *p, const oc_event *ev, int32_t n_events, uint64_t fi
         }
     }
     if (pairs) *pairs = total_pairs;
+    if (hole_steps) *hole_steps = total_hs;
     free(off);
     return worst;
 }

@@ -70,7 +70,7 @@ class ct_run_stats(C.Structure):
         ("steps", C.c_int64), ("pairs", C.c_uint64), ("n_total", C.c_int64), ("n_active", C.c_int64),
         ("field_launches", C.c_int64), ("field_kernel_ms", C.c_double), ("step_wall_ms", C.c_double),
         ("targets_per_thread", C.c_int32), ("block_size", C.c_int32), ("chunk_len", C.c_int32),
-        ("reserved", C.c_int32),
+        ("reserved", C.c_int32), ("hole_steps", C.c_uint64),
     ]
 
 
@@ -332,6 +332,7 @@ class Simulator:
         off = np.zeros(self.batch.n_events + 1, dtype=np.int64)
         np.cumsum(self.counts, out=off[1:])
         return {"pix": pix, "xyz": xyz, "cstep": cstep, "steps": esteps, "pairs": int(stats.pairs),
+                "hole_steps": int(stats.hole_steps),
                 "stats": stats, "offsets": off, "n": self.counts.astype(np.int64)}
 
     def field(self) -> np.ndarray:

@@ -133,7 +133,8 @@ double initial_sigma(const ct_event_desc &e)
 // Byte layout of one batch inside a single device buffer.
 struct Layout {
     size_t off, n_act, ev_step, ev_taken, ref, pos, idx, rngid, out_xyz, out_cstep, pix, pairs,
-        active, item_base, n_items, counter, sigma, dep_off, deposits, x_off, xyz_in, start, total;
+        hsteps, active, item_base, n_items, counter, sigma, dep_off, deposits, x_off, xyz_in, start,
+        total;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -159,6 +160,7 @@ Layout make_layout(int64_t B, int64_t N, int64_t n_dep, int64_t n_exp, int G1)
     L.out_cstep = take(sizeof(int32_t) * N);
     L.pix = take(sizeof(int32_t) * B * G1);
     L.pairs = take(sizeof(uint64_t) * B);
+    L.hsteps = take(sizeof(uint64_t) * B);
     L.active = take(sizeof(int64_t));
     L.item_base = take(sizeof(int32_t) * B);
     L.n_items = take(sizeof(int32_t));
@@ -713,6 +715,7 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     bt.out_cstep = at<int32_t>(w, L.out_cstep);
     bt.pix = at<int32_t>(w, L.pix);
     bt.pairs = at<uint64_t>(w, L.pairs);
+    bt.hsteps = at<uint64_t>(w, L.hsteps);
     bt.active = at<int64_t>(w, L.active);
     bt.item_base = at<int32_t>(w, L.item_base);
     bt.n_items = at<int32_t>(w, L.n_items);
@@ -743,6 +746,7 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     CT_HIP(up(bt.ref, ref.data(), sizeof(double) * 4 * s.B));
     CT_HIP(up((void *)bt.rngid, rngid.data(), sizeof(int32_t) * s.N));
     CT_HIP(up(bt.pairs, zeros64.data(), sizeof(uint64_t) * s.B));
+    CT_HIP(up(bt.hsteps, zeros64.data(), sizeof(uint64_t) * s.B));
     CT_HIP(up(bt.active, zeros64.data(), sizeof(int64_t)));
     CT_HIP(up((void *)bt.sigma, sigma.data(), sizeof(double) * s.B));
     CT_HIP(up((void *)bt.dep_off, dep_off.data(), sizeof(int32_t) * (s.B + 1)));
@@ -854,15 +858,19 @@ ct_status ct_collect(ct_ctx *c, int32_t *pixel_counts, double *xyz, int32_t *col
     if (event_steps && B)
         CT_HIP(hipMemcpyAsync(event_steps, c->bt.ev_taken, sizeof(int64_t) * B,
                               hipMemcpyDeviceToHost, sm));
-    std::vector<uint64_t> pairs(B);
-    if (stats && B)
+    std::vector<uint64_t> pairs(B), hsteps(B);
+    if (stats && B) {
         CT_HIP(hipMemcpyAsync(pairs.data(), c->bt.pairs, sizeof(uint64_t) * B,
                               hipMemcpyDeviceToHost, sm));
+        CT_HIP(hipMemcpyAsync(hsteps.data(), c->bt.hsteps, sizeof(uint64_t) * B,
+                              hipMemcpyDeviceToHost, sm));
+    }
     CT_HIP(hipStreamSynchronize(sm));
     if (stats) {
         ct_run_stats r{};
         r.steps = c->steps;
         for (uint64_t v : pairs) r.pairs += v;
+        for (uint64_t v : hsteps) r.hole_steps += v;
         r.n_total = N;
         r.n_active = c->n_active;
         r.field_launches = c->field_launches;

@@ -49,7 +49,8 @@ struct DevBatch {
     double *out_xyz;        // [N][3] by carrier
     int32_t *out_cstep;     // [N] by carrier
     int32_t *pix;           // [B][grid_n^2 + 1]
-    uint64_t *pairs;        // [B]
+    uint64_t *pairs;        // [B] sum over steps of N_a (N_a - 1)
+    uint64_t *hsteps;       // [B] sum over steps of N_a
     int64_t *active;        // [1] drifting holes after the last compaction
     double *part;           // [nsplit][3][N] partial fields of split events
     int32_t part_chunks;    // chunks the partial buffer holds

@@ -503,6 +503,7 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(DevParams dp, DevBa
         bt.n_act[b] = kept;
         if (count_step && n > 0) {
             bt.pairs[b] += (uint64_t)n * (uint64_t)(n - 1);
+            bt.hsteps[b] += (uint64_t)n;
             bt.ev_step[b] += 1;
             bt.ev_taken[b] += 1;
         }

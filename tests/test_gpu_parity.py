@@ -168,6 +168,7 @@ def test_single_8kev_fp64(ct):
     g = gpu_run(ct, s, b, FP64)
     err = assert_fp64_parity(g, o, "single_8kev fp64")
     assert g["pairs"] == o["pairs"] and np.array_equal(g["steps"], o["steps"])
+    assert g["hole_steps"] == o["hole_steps"]
     print(f"single_8kev fp64: max endpoint error {err:.3e} um, steps {o['steps'][0]}")
 
 
