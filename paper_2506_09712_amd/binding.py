@@ -23,7 +23,9 @@ except Exception:  # pragma: no cover - torch is part of the image
     _HAVE_TORCH = False
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libct.so")
+# CT_LIBRARY selects another build of the same library (e.g. a variant of the
+# kernels compiled with different tuning macros)
+LIB_PATH = os.environ.get("CT_LIBRARY") or os.path.join(_PKG, "libct.so")
 
 CT_ABI_VERSION = 1
 CT_OK, CT_EINVAL, CT_ESTATE, CT_ENOMEM, CT_EDEVICE, CT_EMAXSTEPS, CT_ENONFINITE = 0, -1, -2, -3, -4, -5, -6

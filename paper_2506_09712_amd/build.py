@@ -27,9 +27,9 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, extra_flags=None) -> str:
-    """Compile every source to an object, link libct.so; returns its path."""
-    objdir = os.path.join(PKG, "_build")
+def build(verbose: bool = False, extra_flags=None, out: str = LIB) -> str:
+    """Compile every source to an object, link libct.so (or `out`); returns its path."""
+    objdir = os.path.join(PKG, "_build", os.path.basename(out))
     os.makedirs(objdir, exist_ok=True)
     flags = HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC] + list(extra_flags or [])
     procs = []
@@ -44,18 +44,18 @@ def build(verbose: bool = False, extra_flags=None) -> str:
                                             text=True)))
     failed = False
     for cmd, p in procs:
-        out, _ = p.communicate()
-        if out.strip():
-            print(out, file=sys.stderr)
+        log, _ = p.communicate()
+        if log.strip():
+            print(log, file=sys.stderr)
         if p.returncode != 0:
             failed = True
     if failed:
         raise RuntimeError("hipcc failed")
-    tmp = LIB + f".tmp{os.getpid()}"
+    tmp = out + f".tmp{os.getpid()}"
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
