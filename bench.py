@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--launch", default="", help="kt,bs,chunk override")
+    ap.add_argument("--launch", default="", help="targets_per_thread,block,chunk_len override")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time launch shapes on the seeded state")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -49,11 +49,12 @@ def parse():
     return ap.parse_args()
 
 
-# Algorithmic HBM bytes of one hole update in the step kernel: the target's
+# Algorithmic HBM bytes of one hole update in the step kernel: the hole's
 # FP64 position (24 B) and carrier index (4 B) read, its RNG id (4 B) read,
-# the new FP64 position (24 B) written.  Sources are re-read from cache.
+# the new FP64 position (24 B) written.  Sources are re-reads of the same
+# event's positions, served from cache.
 ALG_BYTES_PER_HOLE_STEP = 56
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_step_f32_batch_8kev_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_run_f32_batch_8kev_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2506_09712_amd", "csrc", "ct_kernels.hip")
 
 
@@ -116,8 +117,10 @@ def main():
 
     tune = ct.CT_OPT_AUTOTUNE if (a.autotune and not launch) else 0
 
-    def timed_runs(options, label):
-        sim = ct.Simulator(sensor, ct.CT_FP32, device=0, options=options | tune, launch=launch)
+    def timed_runs(label):
+        # HIP events around the one step-kernel run of each ct_step call
+        sim = ct.Simulator(sensor, ct.CT_FP32, device=0, options=ct.CT_OPT_TIMING | tune,
+                           launch=launch)
         for _ in range(a.warmup):
             simulate(ct, sim, batch)
         torch.cuda.synchronize()
@@ -137,15 +140,11 @@ def main():
               f"events/s", file=sys.stderr, flush=True)
         return pairs, wall, kern_ms, launches, st, hsteps
 
-    # production path: captured step loop, all events in one launch per step
-    pairs, wall, _, _, st, _ = timed_runs(0, "fp32-batched (graph)")
+    pairs, wall, kern_ms, launches, st, hsteps = timed_runs("fp32-batched")
     value = pairs / wall
     events_per_s = batch.n_events * a.steps / wall
-    # same runs with HIP events around every step-kernel launch (eager issue)
-    tpairs, twall, kern_ms, launches, _, thsteps = timed_runs(ct.CT_OPT_TIMING,
-                                                              "fp32-batched (eager, timed)")
-    traffic, traffic_note = measured_traffic(thsteps / max(launches, 1))
-    achieved = FLOP_PER_PAIR * tpairs / (kern_ms * 1e-3) if kern_ms > 0 else None
+    traffic, traffic_note = measured_traffic(hsteps / max(launches, 1))
+    achieved = FLOP_PER_PAIR * pairs / (kern_ms * 1e-3) if kern_ms > 0 else None
     print(f"bench: step kernel {kern_ms / max(launches, 1):.3f} ms avg over {launches} launches, "
           f"{achieved / 1e12 if achieved else 0:.1f} TFLOP/s", file=sys.stderr, flush=True)
 
@@ -157,24 +156,25 @@ def main():
         "config": {"workload": f"{a.workload}: {batch.n_events} events, "
                                f"{int(batch.n_carriers.sum())} holes, "
                                f"{sensor.thickness_um:g} um Si at {sensor.v_bias:g} V, "
-                               f"dt {sensor.dt_ns:g} ns; FP32 field, FP64 state, all events "
-                               f"in one launch per step",
+                               f"dt {sensor.dt_ns:g} ns; FP32 field, FP64 state; one "
+                               f"persistent step kernel per run, events stepped "
+                               f"independently through a device work queue",
                    "events": batch.n_events, "holes": int(batch.n_carriers.sum()),
                    "launch": {"targets_per_thread": st.targets_per_thread,
-                              "block": st.block_size, "chunk_len": st.chunk_len}},
+                              "block": st.block_size, "chunk_len": st.chunk_len,
+                              "workgroups": st.workgroups}},
         "events_per_s": events_per_s,
         "pairs_per_run": pairs // a.steps,
-        "hole_steps_per_run": thsteps // a.steps,
+        "hole_steps_per_run": hsteps // a.steps,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12 if achieved else None,
                      "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VECTOR_PEAK if achieved else None,
                      "traffic": traffic, "traffic_note": traffic_note,
-                     "algorithmic_bytes_per_launch": ALG_BYTES_PER_HOLE_STEP * thsteps / max(launches, 1),
-                     "hole_steps_per_launch": thsteps / max(launches, 1),
-                     "kernel": "k_step<1,256,fp32>", "avg_launch_ms": kern_ms / max(launches, 1),
-                     "launches": launches, "flop_per_pair": FLOP_PER_PAIR,
-                     "timed_pass": {"value": tpairs / twall, "note": "same runs issued eagerly "
-                                    "with HIP events around each step-kernel launch"}},
+                     "algorithmic_bytes_per_launch": ALG_BYTES_PER_HOLE_STEP * hsteps / max(launches, 1),
+                     "hole_steps_per_launch": hsteps / max(launches, 1),
+                     "kernel": f"k_run_f32<{st.targets_per_thread},{st.block_size}>",
+                     "avg_launch_ms": kern_ms / max(launches, 1),
+                     "launches": launches, "flop_per_pair": FLOP_PER_PAIR},
     }
 
     if not a.no_plain:

@@ -58,9 +58,13 @@ typedef enum {
 } ct_status;
 
 /* Arithmetic of the pairwise field.  Positions and the time integration are
- * FP64 in both modes.  CT_FP32: the field sum runs in FP32 on coordinates
- * relative to the event centroid, with per-tile FP32 partial sums folded
- * into FP64 accumulators. */
+ * FP64 in both modes.  CT_FP32: the pair terms are summed in FP32 on
+ * coordinates relative to the event centroid over each LDS tile of sources,
+ * and the tile sums are added in FP64; CT_FP64: everything in FP64 on
+ * absolute coordinates.  An event's sources are split into chunks whose
+ * length depends only on the event's own hole count and the launch
+ * configuration (ct_set_launch), and the chunk sums are added in chunk
+ * order, so an event's result does not depend on the rest of the batch. */
 typedef enum { CT_FP64 = 0, CT_FP32 = 1 } ct_precision;
 
 /* Mobility model.  CT_MOB_JACOBONI: mu = mu0 / (1 + (E/Ec)^beta)^(1/beta),
@@ -74,11 +78,11 @@ enum { CT_REPULSION = 1u, CT_DRIFT = 2u, CT_DIFFUSION = 4u };
 
 /* options bits */
 enum {
-    CT_OPT_TIMING = 1u,  /* time every repulsion-step kernel with HIP events (ct_run_stats) */
-    CT_OPT_NO_GRAPH = 2u, /* issue every step eagerly instead of replaying a captured graph */
-    CT_OPT_AUTOTUNE = 4u  /* on seeding, time the launch configurations on the seeded state and
-                             keep the fastest (cached per precision and batch-shape bucket);
-                             the chosen configuration sets the summation order of the field */
+    CT_OPT_TIMING = 1u,   /* time every run of the step kernel with HIP events (ct_run_stats) */
+    CT_OPT_AUTOTUNE = 4u  /* on seeding, time the launch configurations on one field evaluation
+                             of the seeded state and keep the fastest (cached per precision and
+                             batch-shape bucket); the chosen configuration sets the grouping of
+                             the field sum (see ct_set_launch) */
 };
 
 typedef struct {
@@ -123,17 +127,18 @@ typedef struct {
 } ct_event_desc;
 
 typedef struct {
-    int64_t steps;             /* steps issued by ct_step since seeding */
+    int64_t steps;             /* sum over ct_step calls of the most steps any event took */
     uint64_t pairs;            /* sum over steps and events of N_a (N_a - 1) */
     int64_t n_total;           /* carriers in the batch */
     int64_t n_active;          /* carriers still drifting */
-    int64_t field_launches;    /* repulsion-step kernel launches timed (CT_OPT_TIMING) */
+    int64_t field_launches;    /* runs of the step kernel timed (CT_OPT_TIMING); one per
+                                  ct_step call unless its work queue filled up */
     double field_kernel_ms;    /* their summed duration, HIP events on the context's stream */
     double step_wall_ms;       /* host wall time spent inside ct_step */
     int32_t targets_per_thread;/* launch configuration in use */
     int32_t block_size;
-    int32_t chunk_len;         /* longest source chunk of a work item (0 = events not split) */
-    int32_t reserved;
+    int32_t chunk_len;         /* source chunk length (ct_set_launch) */
+    int32_t workgroups;        /* resident workgroups of the step kernel */
     uint64_t hole_steps;       /* sum over steps and events of N_a (hole updates performed) */
 } ct_run_stats;
 
@@ -160,11 +165,20 @@ ct_status ct_bind_workspace(ct_ctx *c, void *device_ptr, size_t bytes);
 ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
                          uint64_t first_event_id);
 
-/* Advance every event until all holes are collected or max_steps steps have
- * been issued by this call (max_steps <= 0: the context's max_steps).
- * steps_done (nullable): the most steps any event took in this call;
+/* Advance every event until all its holes are collected or it has taken
+ * max_steps steps in this call (max_steps <= 0: the context's max_steps).
+ * Events advance independently: one persistent kernel works through a
+ * device queue of (event, target tile, source chunk) items, and finishing an
+ * event's step queues its next one, with no device-wide barrier between
+ * steps.  steps_done (nullable): the most steps any event took in this call;
  * n_active (nullable): holes still drifting.  Returns CT_OK when none is
- * left, CT_EMAXSTEPS otherwise (state kept; call again to continue). */
+ * left, CT_EMAXSTEPS otherwise (state kept; call again to continue).  The
+ * queue holds about 512 steps of the batch at its seeded size (environment
+ * variable CT_QUEUE_STEPS, read at seeding, sets another count); when it
+ * fills, the events it cannot take are parked and run again by the same
+ * call, which costs time but never changes results.  If no event step is
+ * queued and no event finishes for 10 s, the kernel stops and the call
+ * returns CT_EDEVICE (the context must then be destroyed). */
 ct_status ct_step(ct_ctx *c, int64_t max_steps, int64_t *steps_done, int64_t *n_active);
 
 /* Copy results to host arrays (each nullable):
@@ -189,9 +203,14 @@ ct_status ct_field(ct_ctx *c, double *field);
 ct_status ct_philox(ct_ctx *c, const uint32_t *counters, int64_t n, uint32_t *words,
                     double *normals);
 
-/* Override the launch configuration (targets per thread 1, 2 or 4; block
- * size 64..1024, multiple of 64; chunk_len >= block size, multiple of it,
- * or 0 for no source splitting).  0 leaves a value unchanged. */
+/* Override the launch configuration: targets per thread (1, 2 or 4), block
+ * size (64, 128 or 256; also the number of sources per LDS tile) and the
+ * source chunk length (a multiple of the block size, at most 2^20): an event
+ * of n holes is split into ceil(n / len) chunks of len sources, len being
+ * chunk_len or, for events of more than 256 chunks, the shortest whole number
+ * of tiles that keeps 256 chunks.  Each chunk of each target tile is one work
+ * item.  0 leaves a value unchanged.  The block size and the chunk length set
+ * the grouping of the field sum, so they change results within rounding. */
 ct_status ct_set_launch(ct_ctx *c, int32_t targets_per_thread, int32_t block_size,
                         int32_t chunk_len);
 

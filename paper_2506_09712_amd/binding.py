@@ -33,7 +33,6 @@ CT_FP64, CT_FP32 = 0, 1
 CT_MOB_JACOBONI, CT_MOB_CONSTANT = 0, 1
 CT_REPULSION, CT_DRIFT, CT_DIFFUSION = 1, 2, 4
 CT_OPT_TIMING = 1
-CT_OPT_NO_GRAPH = 2
 CT_OPT_AUTOTUNE = 4
 
 _STATUS = {0: "CT_OK", -1: "CT_EINVAL", -2: "CT_ESTATE", -3: "CT_ENOMEM", -4: "CT_EDEVICE",
@@ -72,7 +71,7 @@ class ct_run_stats(C.Structure):
         ("steps", C.c_int64), ("pairs", C.c_uint64), ("n_total", C.c_int64), ("n_active", C.c_int64),
         ("field_launches", C.c_int64), ("field_kernel_ms", C.c_double), ("step_wall_ms", C.c_double),
         ("targets_per_thread", C.c_int32), ("block_size", C.c_int32), ("chunk_len", C.c_int32),
-        ("reserved", C.c_int32), ("hole_steps", C.c_uint64),
+        ("workgroups", C.c_int32), ("hole_steps", C.c_uint64),
     ]
 
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -85,6 +86,8 @@ ct_status check_params(const ct_sensor_params *p)
     if ((p->physics_flags & CT_DRIFT) && !(p->v_bias > p->v_dep && p->v_dep >= 0.0))
         return fail(CT_EINVAL, "the linear drift field needs 0 <= v_dep < v_bias (Eq. 6)");
     if (p->max_steps <= 0) return fail(CT_EINVAL, "max_steps must be > 0");
+    if (p->options & ~(uint32_t)(CT_OPT_TIMING | CT_OPT_AUTOTUNE))
+        return fail(CT_EINVAL, "unknown option bits 0x%x", p->options);
     double mu0, ec, beta;
     hole_mobility_params(*p, mu0, ec, beta);
     if (!(mu0 > 0.0) || !(ec > 0.0) || !(beta > 0.0) || !std::isfinite(mu0))
@@ -132,9 +135,8 @@ double initial_sigma(const ct_event_desc &e)
 
 // Byte layout of one batch inside a single device buffer.
 struct Layout {
-    size_t off, n_act, ev_step, ev_taken, ref, pos, idx, rngid, out_xyz, out_cstep, pix, pairs,
-        hsteps, active, item_base, n_items, counter, sigma, dep_off, deposits, x_off, xyz_in, start,
-        total;
+    size_t off, n_act, ev_step, ev_taken, call_steps, ref, pos, idx, rngid, out_xyz, out_cstep, pix,
+        pairs, hsteps, sigma, dep_off, deposits, x_off, xyz_in, start, total;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -152,6 +154,7 @@ Layout make_layout(int64_t B, int64_t N, int64_t n_dep, int64_t n_exp, int G1)
     L.n_act = take(sizeof(int32_t) * B);
     L.ev_step = take(sizeof(int64_t) * B);
     L.ev_taken = take(sizeof(int64_t) * B);
+    L.call_steps = take(sizeof(int64_t) * B);
     L.ref = take(sizeof(double) * 4 * B);
     L.pos = take(sizeof(double) * 6 * N);
     L.idx = take(sizeof(int32_t) * N);
@@ -161,10 +164,6 @@ Layout make_layout(int64_t B, int64_t N, int64_t n_dep, int64_t n_exp, int G1)
     L.pix = take(sizeof(int32_t) * B * G1);
     L.pairs = take(sizeof(uint64_t) * B);
     L.hsteps = take(sizeof(uint64_t) * B);
-    L.active = take(sizeof(int64_t));
-    L.item_base = take(sizeof(int32_t) * B);
-    L.n_items = take(sizeof(int32_t));
-    L.counter = take(sizeof(uint32_t));
     L.sigma = take(sizeof(double) * B);
     L.dep_off = take(sizeof(int32_t) * (B + 1));
     L.deposits = take(sizeof(double) * 3 * n_dep);
@@ -211,20 +210,75 @@ ct_status shape_of(const ct_sensor_params &p, const ct_event_desc *ev, int32_t B
     return CT_OK;
 }
 
-// Launch configuration of a new context (ct_set_launch overrides it).
+// Launch configuration of a new context (ct_set_launch overrides it): one
+// target per thread, 256-thread workgroups, sources in chunks of 768.
 ct::LaunchCfg default_cfg(const ct_sensor_params &p)
 {
-    // measured best on 256 events of 2222 holes (one target per thread,
-    // 256-thread workgroups, sources split into chunks of <= 768 / 512)
-    return p.precision == CT_FP32 ? ct::LaunchCfg{1, 256, 768} : ct::LaunchCfg{1, 256, 512};
+    (void)p;
+    return ct::LaunchCfg{1, 256, 768};
 }
 
-constexpr int kGraphSteps = 16;  // steps per captured graph (and per host poll)
+// Tickets the work queue holds per run: about 512 steps of the batch at its
+// initial size (the environment variable CT_QUEUE_STEPS overrides the 512),
+// at least one step, at most 2^25 tickets; a run that fills it parks the
+// events it could not queue and the host runs again.
+constexpr int64_t kQueueSteps = 512;
+constexpr int64_t kQueueMax = int64_t(1) << 25;
 
-int default_chunks(int chunk, int32_t n_max)
+int64_t queue_steps()
 {
-    if (chunk <= 0 || n_max <= chunk) return 1;
-    return (n_max + chunk - 1) / chunk;
+    const char *v = std::getenv("CT_QUEUE_STEPS");
+    if (!v || !*v) return kQueueSteps;
+    const long long k = std::atoll(v);
+    return k >= 1 ? (int64_t)k : kQueueSteps;
+}
+
+// Work queue, completion counters and partial-field buffer of a batch for a
+// launch configuration, in one device allocation.
+struct QueueLayout {
+    size_t sched, q, seq, tiles_left, chunks_left, tile_base, part_off, part, total;
+    uint32_t cap;
+    std::vector<int32_t> tile_base_h;
+    std::vector<int64_t> part_off_h;
+};
+
+QueueLayout make_queue_layout(const BatchShape &s, const ct::LaunchCfg &cfg, bool repulsion)
+{
+    QueueLayout Q{};
+    const int64_t T = (int64_t)cfg.kt * cfg.bs;
+    Q.tile_base_h.assign(s.B + 1, 0);
+    Q.part_off_h.assign(s.B + 1, 0);
+    int64_t items = 0;
+    for (int64_t b = 0; b < s.B; ++b) {
+        const int64_t n0 = s.n[b];
+        const int64_t tiles = (n0 + T - 1) / T;
+        // chunks of any later (smaller) count stay within this bound
+        int64_t chunks = 1;
+        if (repulsion && n0 > 0)
+            chunks = std::min<int64_t>((n0 + cfg.chunk - 1) / cfg.chunk, ct::kMaxChunks);
+        Q.tile_base_h[b + 1] = Q.tile_base_h[b] + (int32_t)tiles;
+        Q.part_off_h[b + 1] = Q.part_off_h[b] + (chunks > 1 ? 3 * n0 * chunks : 0);
+        items += tiles * chunks;
+    }
+    int64_t cap = std::max<int64_t>(items, std::min<int64_t>(items * queue_steps(), kQueueMax));
+    cap = std::max<int64_t>(cap, 1);
+    Q.cap = (uint32_t)cap;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    Q.sched = take(sizeof(ct::Sched));
+    Q.q = take(sizeof(ct::QItem) * cap);
+    Q.seq = take(sizeof(uint32_t) * cap);
+    Q.tiles_left = take(sizeof(int32_t) * s.B * ct::kEventLine);
+    Q.chunks_left = take(sizeof(int32_t) * Q.tile_base_h[s.B]);
+    Q.tile_base = take(sizeof(int32_t) * (s.B + 1));
+    Q.part_off = take(sizeof(int64_t) * (s.B + 1));
+    Q.part = take(sizeof(double) * Q.part_off_h[s.B]);
+    Q.total = o;
+    return Q;
 }
 
 }  // namespace
@@ -233,11 +287,13 @@ struct ct_ctx {
     ct_sensor_params p{};
     ct::DevParams dp{};
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // the caller's stream, or one of ours
     bool own_stream = false;
-    ct::LaunchCfg cfg{2, 256, 0};
+    ct::LaunchCfg cfg{1, 256, 768};
+    int cu_count = 0;
+    int grid = 0;  // resident workgroups of the run kernel for cfg
 
-    // device workspace
+    // device workspace (the batch)
     void *ws = nullptr;
     size_t ws_bytes = 0;
     bool ws_bound = false;
@@ -245,19 +301,13 @@ struct ct_ctx {
     size_t bound_bytes = 0;
     double *field_buf = nullptr;
     size_t field_buf_n = 0;
-    double *part_buf = nullptr;  // partial fields of split events (library-owned)
-    size_t part_cap = 0;         // doubles
-    ct::Item *work_buf = nullptr;  // step work list (library-owned)
-    size_t work_cap = 0;
-    int cu_count = 0;
-    int grid = 0;                // persistent step-kernel workgroups for cfg
 
-    // captured step loop, reused while the batch layout and launch are unchanged
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    ct::DevBatch graph_bt{};
-    ct::LaunchCfg graph_cfg{};
-    int graph_grid = 0;
+    // work queue of the batch for cfg
+    void *qbuf = nullptr;
+    size_t qbuf_bytes = 0;
+    ct::DevQueue dq{};
+    uint32_t gen = 0;
+    bool broken = false;  // a run reported an error; only ct_destroy is allowed
 
     // batch
     bool seeded = false;
@@ -267,8 +317,8 @@ struct ct_ctx {
     int64_t n_active = 0;
     int64_t steps = 0;
 
-    int64_t *h_pinned = nullptr;  // [0] active count
-    hipEvent_t ev_a[64] = {}, ev_b[64] = {};
+    ct::Sched *h_sched = nullptr;  // pinned copy of the control block
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
     int64_t field_launches = 0;
     double field_ms = 0.0;
     double step_wall_ms = 0.0;
@@ -311,59 +361,6 @@ ct_status ensure_workspace(ct_ctx *c, size_t bytes)
     return CT_OK;
 }
 
-// Partial-field buffer for events split into source chunks: [chunks][3][N].
-ct_status ensure_part(ct_ctx *c, const ct::LaunchCfg &cfg, int64_t N, int32_t n_max)
-{
-    const int chunks = default_chunks(cfg.chunk, n_max);
-    const size_t need = chunks > 1 ? (size_t)3 * N * chunks : 0;
-    if (need > c->part_cap) {
-        if (c->part_buf) CT_HIP(hipFree(c->part_buf));
-        c->part_buf = nullptr;
-        c->part_cap = 0;
-        if (hipMalloc((void **)&c->part_buf, need * sizeof(double)) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(CT_ENOMEM, "partial-field buffer of %zu bytes failed", need * sizeof(double));
-        }
-        c->part_cap = need;
-    }
-    c->bt.part = c->part_buf;
-    c->bt.part_chunks = chunks;
-    return CT_OK;
-}
-
-int64_t work_items_for(const ct::LaunchCfg &cfg, const std::vector<int32_t> &n)
-{
-    const int64_t T = (int64_t)cfg.bs * cfg.kt;
-    int64_t items = 0;
-    for (int32_t v : n)
-        if (v > 0) items += ((v + T - 1) / T) * (cfg.chunk > 0 ? (v + cfg.chunk - 1) / cfg.chunk : 1);
-    return items;
-}
-
-// Work-list buffer sized for the batch's initial sizes (holes only retire,
-// so later steps need fewer items) and the persistent grid for cfg.
-ct_status ensure_work(ct_ctx *c, const ct::LaunchCfg &cfg, const std::vector<int32_t> &n)
-{
-    const int64_t need = std::max<int64_t>(work_items_for(cfg, n), 1);
-    if (need > INT32_MAX) return fail(CT_EINVAL, "work list too long (%lld items)", (long long)need);
-    if ((size_t)need > c->work_cap) {
-        if (c->work_buf) CT_HIP(hipFree(c->work_buf));
-        c->work_buf = nullptr;
-        c->work_cap = 0;
-        if (hipMalloc((void **)&c->work_buf, need * sizeof(ct::Item)) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(CT_ENOMEM, "work list of %lld items failed", (long long)need);
-        }
-        c->work_cap = (size_t)need;
-    }
-    const int occ = ct::step_occupancy(cfg, c->p.precision == CT_FP32);
-    if (occ <= 0) return fail(CT_EDEVICE, "step kernel occupancy query failed");
-    c->grid = occ * c->cu_count;
-    c->bt.work = c->work_buf;
-    c->bt.work_cap = (int32_t)c->work_cap;
-    return CT_OK;
-}
-
 template <class T>
 T *at(void *base, size_t off)
 {
@@ -376,64 +373,88 @@ ct_status set_device(ct_ctx *c)
     return CT_OK;
 }
 
-ct_status sync_active(ct_ctx *c)
+// Work queue of the seeded batch for cfg, and the resident grid.  The queue
+// memory is kept while it is large enough; its sequence words are cleared
+// whenever it is (re)allocated, so no stale ticket can match a generation.
+ct_status prepare_queue(ct_ctx *c, const ct::LaunchCfg &cfg)
 {
-    CT_HIP(hipMemcpyAsync(c->h_pinned, c->bt.active, sizeof(int64_t), hipMemcpyDeviceToHost,
-                          c->stream));
-    CT_HIP(hipStreamSynchronize(c->stream));
-    c->n_active = c->h_pinned[0];
-    return CT_OK;
-}
-
-ct_status drop_graph(ct_ctx *c)
-{
-    if (c->graph_exec) CT_HIP(hipGraphExecDestroy(c->graph_exec));
-    if (c->graph) CT_HIP(hipGraphDestroy(c->graph));
-    c->graph_exec = nullptr;
-    c->graph = nullptr;
-    return CT_OK;
-}
-
-// One time step: work list, pair kernel (+ partial-sum update), compaction.
-// With timing, HIP events bracket the pair kernel (slot i of the event pool).
-hipError_t issue_step(ct_ctx *c, const ct::LaunchCfg &cfg, int slot, bool timing)
-{
-    const int fp32 = c->p.precision == CT_FP32;
-    hipError_t e = ct::launch_plan(c->bt, cfg, c->stream);
-    if (e == hipSuccess && timing) e = hipEventRecord(c->ev_a[slot], c->stream);
-    if (e == hipSuccess) e = ct::launch_step(c->dp, c->bt, cfg, fp32, c->grid, 0, nullptr, c->stream);
-    if (e == hipSuccess && timing) e = hipEventRecord(c->ev_b[slot], c->stream);
-    if (e == hipSuccess) e = ct::launch_update(c->dp, c->bt, cfg, c->shape.n_max, 0, nullptr, c->stream);
-    if (e == hipSuccess) e = ct::launch_compact(c->dp, c->bt, 1, c->stream);
-    return e;
-}
-
-// Capture kGraphSteps steps into one executable graph (per batch and launch
-// configuration); every kernel reads its sizes from device memory, so the
-// same graph serves every chunk of the run.
-ct_status ensure_graph(ct_ctx *c, const ct::LaunchCfg &cfg)
-{
-    if (c->graph_exec && std::memcmp(&c->graph_bt, &c->bt, sizeof c->bt) == 0 &&
-        c->graph_cfg.kt == cfg.kt && c->graph_cfg.bs == cfg.bs && c->graph_cfg.chunk == cfg.chunk &&
-        c->graph_grid == c->grid)
-        return CT_OK;
-    ct_status st = drop_graph(c);
-    if (st != CT_OK) return st;
-    CT_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < kGraphSteps && e == hipSuccess; ++i) e = issue_step(c, cfg, i, false);
-    hipGraph_t g = nullptr;
-    const hipError_t e2 = hipStreamEndCapture(c->stream, &g);
-    if (e != hipSuccess || e2 != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return fail(CT_EDEVICE, "step-loop capture failed: %s",
-                    hipGetErrorString(e != hipSuccess ? e : e2));
+    const bool repulsion = (c->p.physics_flags & CT_REPULSION) != 0;
+    QueueLayout Q = make_queue_layout(c->shape, cfg, repulsion);
+    hipStream_t sm = c->stream;
+    if (Q.total > c->qbuf_bytes) {
+        if (c->qbuf) {
+            CT_HIP(hipStreamSynchronize(sm));
+            CT_HIP(hipFree(c->qbuf));
+        }
+        c->qbuf = nullptr;
+        c->qbuf_bytes = 0;
+        if (hipMalloc(&c->qbuf, Q.total) != hipSuccess) {
+            (void)hipGetLastError();
+            c->qbuf = nullptr;
+            return fail(CT_ENOMEM, "work queue of %zu bytes failed", Q.total);
+        }
+        c->qbuf_bytes = Q.total;
+        CT_HIP(ct::launch_fill_i32((int32_t *)c->qbuf, (int64_t)(c->qbuf_bytes / 4), 0, sm));
+    } else {
+        // the sequence words move with the layout: clear them for this one
+        CT_HIP(ct::launch_fill_i32(at<int32_t>(c->qbuf, Q.seq), (int64_t)Q.cap, 0, sm));
     }
-    c->graph = g;
-    CT_HIP(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
-    c->graph_bt = c->bt;
-    c->graph_cfg = cfg;
-    c->graph_grid = c->grid;
+    ct::DevQueue d{};
+    d.sc = at<ct::Sched>(c->qbuf, Q.sched);
+    d.q = at<ct::QItem>(c->qbuf, Q.q);
+    d.seq = at<uint32_t>(c->qbuf, Q.seq);
+    d.cap = Q.cap;
+    d.tiles_left = at<int32_t>(c->qbuf, Q.tiles_left);
+    d.chunks_left = at<int32_t>(c->qbuf, Q.chunks_left);
+    d.tile_base = at<int32_t>(c->qbuf, Q.tile_base);
+    d.part = at<double>(c->qbuf, Q.part);
+    d.part_off = at<int64_t>(c->qbuf, Q.part_off);
+    if (c->shape.B > 0) {
+        CT_HIP(hipMemcpyAsync((void *)d.tile_base, Q.tile_base_h.data(),
+                              sizeof(int32_t) * (c->shape.B + 1), hipMemcpyHostToDevice, sm));
+        CT_HIP(hipMemcpyAsync((void *)d.part_off, Q.part_off_h.data(),
+                              sizeof(int64_t) * (c->shape.B + 1), hipMemcpyHostToDevice, sm));
+        CT_HIP(hipStreamSynchronize(sm));  // host vectors go out of scope
+    }
+    c->dq = d;
+    const int occ = ct::run_occupancy(cfg, c->p.precision == CT_FP32);
+    if (occ <= 0) return fail(CT_EDEVICE, "run kernel occupancy query failed");
+    c->grid = occ * c->cu_count;
+    return CT_OK;
+}
+
+// One run of the persistent kernel: queue the first step of every eligible
+// event, run until every event is finished or parked, then read back the
+// control block (and the drifting-hole count and steps taken).
+ct_status run_once(ct_ctx *c, const ct::LaunchCfg &cfg, int64_t max_steps, int field_only,
+                   double *field_out, bool timing)
+{
+    if (++c->gen == 0) ++c->gen;  // 0 is the cleared state of a sequence word
+    c->dq.gen = c->gen;
+    const int fp32 = c->p.precision == CT_FP32;
+    const int repulsion = (c->p.physics_flags & CT_REPULSION) != 0;
+    hipStream_t sm = c->stream;
+    CT_HIP(ct::launch_init(c->bt, c->dq, cfg, max_steps, field_only, repulsion, sm));
+    if (timing) CT_HIP(hipEventRecord(c->ev_a, sm));
+    CT_HIP(ct::launch_run(c->dp, c->bt, c->dq, cfg, fp32, c->grid, max_steps, field_only, field_out,
+                          sm));
+    if (timing) CT_HIP(hipEventRecord(c->ev_b, sm));
+    CT_HIP(ct::launch_summary(c->bt, c->dq.sc, sm));
+    CT_HIP(hipMemcpyAsync(c->h_sched, c->dq.sc, sizeof(ct::Sched), hipMemcpyDeviceToHost, sm));
+    CT_HIP(hipStreamSynchronize(sm));
+    if (timing) {
+        float ms = 0.0f;
+        CT_HIP(hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
+        c->field_ms += ms;
+        c->field_launches += 1;
+    }
+    if (c->h_sched->error.v) {
+        c->broken = true;
+        return fail(CT_EDEVICE, "%s", c->h_sched->error.v == 2u
+                                          ? "work queue too small for the first step (internal error)"
+                                          : "step kernel stopped: no event step queued or finished "
+                                            "for 10 s");
+    }
     return CT_OK;
 }
 
@@ -451,8 +472,16 @@ ct_status ensure_field_buf(ct_ctx *c, int64_t N)
     return CT_OK;
 }
 
-// Launch configurations chosen by the autotuner, per precision and batch
-// shape bucket (events, largest event, total holes; powers of two).
+// The field the next step would apply, into field_buf (NaN for collected).
+ct_status field_into_buf(ct_ctx *c, const ct::LaunchCfg &cfg, bool timing)
+{
+    const int64_t N = c->shape.N;
+    CT_HIP(ct::launch_fill_i32((int32_t *)c->field_buf, 6 * N, (int32_t)0xFFFFFFFF, c->stream));
+    return run_once(c, cfg, INT64_MAX, 1, c->field_buf, timing);
+}
+
+// Launch configurations chosen by the autotuner, per precision, device and
+// batch shape bucket (events, largest event, total holes; powers of two).
 using TuneKey = std::tuple<int, int, int, int, int>;
 std::map<TuneKey, ct::LaunchCfg> g_tuned;
 std::mutex g_tuned_mu;
@@ -467,67 +496,55 @@ int log2_bucket(int64_t v)
     return b;
 }
 
-// Time one field evaluation of the seeded state per candidate (work list,
-// persistent pair kernel, partial-sum update) and keep the fastest.  The
-// state is not advanced.
+// Time one field evaluation of the seeded state per candidate and keep the
+// fastest.  The state is not advanced.
 ct_status autotune(ct_ctx *c)
 {
     const int fp32 = c->p.precision == CT_FP32;
     const TuneKey key{fp32, c->device, log2_bucket(c->shape.B), log2_bucket(c->shape.n_max),
                       log2_bucket(c->shape.N)};
+    ct::LaunchCfg best = c->cfg;
+    bool cached = false;
     {
         std::lock_guard<std::mutex> lk(g_tuned_mu);
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) {
-            ct::LaunchCfg best = it->second;
-            ct_status st = ensure_part(c, best, c->shape.N, c->shape.n_max);
-            if (st == CT_OK) st = ensure_work(c, best, c->shape.n);
-            if (st == CT_OK) c->cfg = best;
-            return st;
+            best = it->second;
+            cached = true;
         }
     }
-    ct_status st = ensure_field_buf(c, c->shape.N);
-    if (st != CT_OK) return st;
-    std::vector<ct::LaunchCfg> cand;
-    for (int bs : {128, 256})
-        for (int chunk : {0, 512, 768, 1024, 2048, 4096}) {
-            if (chunk && (chunk % bs || chunk >= c->shape.n_max)) continue;
-            cand.push_back(ct::LaunchCfg{1, bs, chunk});
-        }
-    cand.push_back(ct::LaunchCfg{2, 128, 0});
-    ct::LaunchCfg best = c->cfg;
-    float best_ms = 1e30f;
-    for (const ct::LaunchCfg &cfg : cand) {
-        st = ensure_part(c, cfg, c->shape.N, c->shape.n_max);
-        if (st == CT_OK) st = ensure_work(c, cfg, c->shape.n);
+    ct_status st;
+    if (!cached) {
+        st = ensure_field_buf(c, c->shape.N);
         if (st != CT_OK) return st;
-        float ms_min = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
-            CT_HIP(hipEventRecord(c->ev_a[0], c->stream));
-            CT_HIP(ct::launch_plan(c->bt, cfg, c->stream));
-            CT_HIP(ct::launch_step(c->dp, c->bt, cfg, fp32, c->grid, 1, c->field_buf, c->stream));
-            CT_HIP(ct::launch_update(c->dp, c->bt, cfg, c->shape.n_max, 1, c->field_buf, c->stream));
-            CT_HIP(hipEventRecord(c->ev_b[0], c->stream));
-            CT_HIP(hipEventSynchronize(c->ev_b[0]));
-            float ms = 0.0f;
-            CT_HIP(hipEventElapsedTime(&ms, c->ev_a[0], c->ev_b[0]));
-            if (rep > 0) ms_min = std::min(ms_min, ms);
+        const std::vector<ct::LaunchCfg> cand = {{1, 256, 512}, {1, 256, 768}, {1, 256, 1024},
+                                                 {1, 128, 512}, {2, 256, 768}};
+        float best_ms = 1e30f;
+        const double ms0 = c->field_ms;
+        const int64_t l0 = c->field_launches;
+        for (const ct::LaunchCfg &cfg : cand) {
+            st = prepare_queue(c, cfg);
+            if (st != CT_OK) return st;
+            float ms_min = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                const double before = c->field_ms;
+                st = field_into_buf(c, cfg, true);
+                if (st != CT_OK) return st;
+                if (rep > 0) ms_min = std::min(ms_min, (float)(c->field_ms - before));
+            }
+            if (ms_min < best_ms) {
+                best_ms = ms_min;
+                best = cfg;
+            }
         }
-        if (ms_min < best_ms) {
-            best_ms = ms_min;
-            best = cfg;
-        }
+        c->field_ms = ms0;
+        c->field_launches = l0;
+        std::lock_guard<std::mutex> lk(g_tuned_mu);
+        g_tuned[key] = best;
     }
-    st = ensure_part(c, best, c->shape.N, c->shape.n_max);
-    if (st == CT_OK) st = ensure_work(c, best, c->shape.n);
+    st = prepare_queue(c, best);
     if (st != CT_OK) return st;
     c->cfg = best;
-    // the field pass reset the drifting-hole total on the device: restore it
-    CT_HIP(hipMemcpyAsync(c->bt.active, &c->n_active, sizeof(int64_t), hipMemcpyHostToDevice,
-                          c->stream));
-    CT_HIP(hipStreamSynchronize(c->stream));
-    std::lock_guard<std::mutex> lk(g_tuned_mu);
-    g_tuned[key] = best;
     return CT_OK;
 }
 
@@ -599,12 +616,10 @@ ct_status ct_init_sensor(const ct_sensor_params *p, ct_ctx **out)
             return bail(fail(CT_EDEVICE, "hipStreamCreate failed"));
         c->own_stream = true;
     }
-    if (hipHostMalloc((void **)&c->h_pinned, 64, hipHostMallocDefault) != hipSuccess)
+    if (hipEventCreate(&c->ev_a) != hipSuccess || hipEventCreate(&c->ev_b) != hipSuccess)
+        return bail(fail(CT_EDEVICE, "hipEventCreate failed"));
+    if (hipHostMalloc((void **)&c->h_sched, sizeof(ct::Sched), hipHostMallocDefault) != hipSuccess)
         return bail(fail(CT_EDEVICE, "hipHostMalloc failed"));
-    for (int i = 0; i < 64; ++i) {
-        if (hipEventCreate(&c->ev_a[i]) != hipSuccess || hipEventCreate(&c->ev_b[i]) != hipSuccess)
-            return bail(fail(CT_EDEVICE, "hipEventCreate failed"));
-    }
     *out = c;
     return CT_OK;
 }
@@ -614,31 +629,30 @@ ct_status ct_bind_workspace(ct_ctx *c, void *device_ptr, size_t bytes)
     if (!c) return fail(CT_EINVAL, "ctx is NULL");
     if (device_ptr && ((uintptr_t)device_ptr & 255u))
         return fail(CT_EINVAL, "workspace must be 256-byte aligned");
-    if (c->seeded && c->ws_bound) c->seeded = false;  // the batch lived in the old buffer
+    if (c->seeded && c->ws_bound && device_ptr != c->ws) c->seeded = false;  // batch lived there
     c->bound_ptr = device_ptr;
     c->bound_bytes = device_ptr ? bytes : 0;
     return CT_OK;
 }
 
-ct_status ct_set_launch(ct_ctx *c, int32_t kt, int32_t bs, int32_t chunk)
+ct_status ct_set_launch(ct_ctx *c, int32_t kt, int32_t bs, int32_t chunk_len)
 {
     if (!c) return fail(CT_EINVAL, "ctx is NULL");
+    if (c->broken) return fail(CT_EDEVICE, "context unusable after a device error");
     ct::LaunchCfg n = c->cfg;
     if (kt) n.kt = kt;
     if (bs) n.bs = bs;
-    if (chunk) n.chunk = chunk < 0 ? 0 : chunk;
+    if (chunk_len) n.chunk = chunk_len;
     if (!ct::launch_supported(n.kt, n.bs))
         return fail(CT_EINVAL, "unsupported launch (targets/thread %d, block %d)", n.kt, n.bs);
-    if (n.chunk > 0 && (n.chunk < n.bs || n.chunk % n.bs))
-        return fail(CT_EINVAL, "chunk_len must be a multiple of the block size");
+    if (!chunk_len && n.chunk % n.bs) n.chunk = (n.chunk + n.bs - 1) / n.bs * n.bs;
+    if (n.chunk < n.bs || n.chunk > (1 << 20) || n.chunk % n.bs)
+        return fail(CT_EINVAL, "chunk_len %d must be a multiple of the block size %d, at most 2^20",
+                    n.chunk, n.bs);
     if (c->seeded) {
         ct_status st = set_device(c);
         if (st != CT_OK) return st;
-        st = ensure_part(c, n, c->shape.N, c->shape.n_max);
-        if (st != CT_OK) return st;
-        st = ensure_work(c, n, c->shape.n);
-        if (st != CT_OK) return st;
-        st = drop_graph(c);
+        st = prepare_queue(c, n);
         if (st != CT_OK) return st;
     }
     c->cfg = n;
@@ -649,9 +663,11 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
                          uint64_t first_event_id)
 {
     if (!c) return fail(CT_EINVAL, "ctx is NULL");
+    if (c->broken) return fail(CT_EDEVICE, "context unusable after a device error");
     BatchShape s;
     ct_status st = shape_of(c->p, ev, n_events, s);
     if (st != CT_OK) return st;
+    if (s.B > 65535) return fail(CT_EINVAL, "at most 65535 events per batch");
     // host-side staging of the event descriptions
     const int G1 = c->p.grid_n * c->p.grid_n + 1;
     std::vector<int32_t> off(s.B + 1), dep_off(s.B + 1), x_off(s.B + 1), rngid(s.N);
@@ -666,7 +682,11 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
         x_off[b + 1] = x_off[b] + (e.n_deposits == 0 ? n : 0);
         sigma[b] = e.n_deposits > 0 ? initial_sigma(e) : 0.0;
         start[b] = e.start_step;
-        for (int32_t d = 0; d < 3 * e.n_deposits; ++d) deps[3 * (size_t)dep_off[b] + d] = e.deposits[d];
+        for (int32_t d = 0; d < 3 * e.n_deposits; ++d) {
+            if (!std::isfinite(e.deposits[d]))
+                return fail(CT_ENONFINITE, "event %d: deposit not finite", b);
+            deps[3 * (size_t)dep_off[b] + d] = e.deposits[d];
+        }
         if (e.n_deposits == 0) {
             for (int64_t d = 0; d < 3 * (int64_t)n; ++d) {
                 const double v = e.xyz[d];
@@ -677,9 +697,6 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
             }
         }
         for (int32_t k = 0; k < n; ++k) rngid[off[b] + k] = e.ids ? e.ids[k] : k;
-        for (int32_t d = 0; d < 3 * e.n_deposits; ++d)
-            if (!std::isfinite(e.deposits[d]))
-                return fail(CT_ENONFINITE, "event %d: deposit not finite", b);
     }
     st = set_device(c);
     if (st != CT_OK) return st;
@@ -687,13 +704,8 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     c->seeded = false;
     st = ensure_workspace(c, L.total);
     if (st != CT_OK) return st;
-    st = ensure_part(c, c->cfg, s.N, s.n_max);
-    if (st != CT_OK) return st;
-    st = ensure_work(c, c->cfg, s.n);
-    if (st != CT_OK) return st;
     void *w = c->ws;
-    ct::DevBatch bt;
-    std::memset(&bt, 0, sizeof bt);  // compared bytewise against the captured graph
+    ct::DevBatch bt{};
     bt.n_events = (int32_t)s.B;
     bt.n_total = (int32_t)s.N;
     bt.first_event_id = first_event_id;
@@ -701,6 +713,7 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     bt.n_act = at<int32_t>(w, L.n_act);
     bt.ev_step = at<int64_t>(w, L.ev_step);
     bt.ev_taken = at<int64_t>(w, L.ev_taken);
+    bt.call_steps = at<int64_t>(w, L.call_steps);
     bt.ref = at<double>(w, L.ref);
     double *pos = at<double>(w, L.pos);
     bt.cx = pos;
@@ -716,20 +729,17 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     bt.pix = at<int32_t>(w, L.pix);
     bt.pairs = at<uint64_t>(w, L.pairs);
     bt.hsteps = at<uint64_t>(w, L.hsteps);
-    bt.active = at<int64_t>(w, L.active);
-    bt.item_base = at<int32_t>(w, L.item_base);
-    bt.n_items = at<int32_t>(w, L.n_items);
-    bt.counter = at<uint32_t>(w, L.counter);
-    bt.work = c->work_buf;
-    bt.work_cap = (int32_t)c->work_cap;
-    bt.part = c->part_buf;
-    bt.part_chunks = default_chunks(c->cfg.chunk, s.n_max);
     bt.sigma = at<double>(w, L.sigma);
     bt.dep_off = at<int32_t>(w, L.dep_off);
     bt.deposits = at<double>(w, L.deposits);
     bt.x_off = at<int32_t>(w, L.x_off);
     bt.xyz_in = at<double>(w, L.xyz_in);
     bt.start = at<int64_t>(w, L.start);
+    c->bt = bt;
+    c->L = L;
+    c->shape = s;
+    st = prepare_queue(c, c->cfg);
+    if (st != CT_OK) return st;
 
     hipStream_t sm = c->stream;
     auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
@@ -738,16 +748,16 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     };
     std::vector<int32_t> n_act(s.n);
     std::vector<double> ref(4 * s.B, 0.0);
-    std::vector<int64_t> zeros64(std::max<int64_t>(s.B, 2), 0);
+    std::vector<int64_t> zeros64(s.B, 0);
     CT_HIP(up((void *)bt.off, off.data(), sizeof(int32_t) * (s.B + 1)));
     CT_HIP(up(bt.n_act, n_act.data(), sizeof(int32_t) * s.B));
     CT_HIP(up(bt.ev_step, start.data(), sizeof(int64_t) * s.B));
     CT_HIP(up(bt.ev_taken, zeros64.data(), sizeof(int64_t) * s.B));
+    CT_HIP(up(bt.call_steps, zeros64.data(), sizeof(int64_t) * s.B));
     CT_HIP(up(bt.ref, ref.data(), sizeof(double) * 4 * s.B));
     CT_HIP(up((void *)bt.rngid, rngid.data(), sizeof(int32_t) * s.N));
     CT_HIP(up(bt.pairs, zeros64.data(), sizeof(uint64_t) * s.B));
     CT_HIP(up(bt.hsteps, zeros64.data(), sizeof(uint64_t) * s.B));
-    CT_HIP(up(bt.active, zeros64.data(), sizeof(int64_t)));
     CT_HIP(up((void *)bt.sigma, sigma.data(), sizeof(double) * s.B));
     CT_HIP(up((void *)bt.dep_off, dep_off.data(), sizeof(int32_t) * (s.B + 1)));
     CT_HIP(up((void *)bt.deposits, deps.data(), sizeof(double) * deps.size()));
@@ -756,16 +766,15 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     CT_HIP(up((void *)bt.start, start.data(), sizeof(int64_t) * s.B));
     CT_HIP(ct::launch_fill_i32(bt.pix, s.B * G1, 0, sm));
     CT_HIP(ct::launch_seed(c->dp, bt, sm));
-    CT_HIP(ct::launch_compact(c->dp, bt, 0, sm));
-    c->bt = bt;
-    c->L = L;
-    c->shape = s;
+    CT_HIP(ct::launch_compact(c->dp, bt, sm));
+    CT_HIP(ct::launch_summary(bt, c->dq.sc, sm));
+    CT_HIP(hipMemcpyAsync(c->h_sched, c->dq.sc, sizeof(ct::Sched), hipMemcpyDeviceToHost, sm));
+    CT_HIP(hipStreamSynchronize(sm));
+    c->n_active = s.B > 0 ? c->h_sched->active : 0;
     c->steps = 0;
     c->field_launches = 0;
     c->field_ms = 0.0;
     c->step_wall_ms = 0.0;
-    st = sync_active(c);
-    if (st != CT_OK) return st;
     c->seeded = true;
     if ((c->p.options & CT_OPT_AUTOTUNE) && (c->p.physics_flags & CT_REPULSION) && s.N > 0) {
         st = autotune(c);
@@ -777,62 +786,34 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
 ct_status ct_step(ct_ctx *c, int64_t max_steps, int64_t *steps_done, int64_t *n_active)
 {
     if (!c) return fail(CT_EINVAL, "ctx is NULL");
+    if (c->broken) return fail(CT_EDEVICE, "context unusable after a device error");
     if (!c->seeded) return fail(CT_ESTATE, "ct_step before ct_seed_events");
     ct_status st = set_device(c);
     if (st != CT_OK) return st;
     if (max_steps <= 0) max_steps = c->p.max_steps;
     const auto t_start = std::chrono::steady_clock::now();
     const bool timing = (c->p.options & CT_OPT_TIMING) != 0;
-    const bool use_graph = !(c->p.options & CT_OPT_NO_GRAPH);
-    std::vector<int64_t> taken0(c->shape.B), taken1(c->shape.B);
-    if (c->shape.B > 0) {
-        CT_HIP(hipMemcpyAsync(taken0.data(), c->bt.ev_taken, sizeof(int64_t) * c->shape.B,
-                              hipMemcpyDeviceToHost, c->stream));
-        CT_HIP(hipStreamSynchronize(c->stream));
-    }
-    ct::LaunchCfg cfg = c->cfg;
-    if (!(c->p.physics_flags & CT_REPULSION)) cfg.chunk = 0;
-    int64_t issued = 0;
-    while (c->n_active > 0 && issued < max_steps) {
-        // one chunk: kGraphSteps captured steps, or the remainder issued eagerly;
-        // steps after the last hole is collected find empty work lists
-        const int k = (int)std::min<int64_t>(kGraphSteps, max_steps - issued);
-        // HIP events recorded inside a graph replay carry no timestamps, so
-        // timed runs issue their steps eagerly
-        if (use_graph && !timing && k == kGraphSteps) {
-            st = ensure_graph(c, cfg);
-            if (st != CT_OK) return st;
-            CT_HIP(hipGraphLaunch(c->graph_exec, c->stream));
-        } else {
-            for (int i = 0; i < k; ++i) CT_HIP(issue_step(c, cfg, i, timing));
-        }
-        issued += k;
-        c->steps += k;
-        st = sync_active(c);
-        if (st != CT_OK) return st;
-        if (timing) {
-            for (int i = 0; i < k; ++i) {
-                float ms = 0.0f;
-                CT_HIP(hipEventElapsedTime(&ms, c->ev_a[i], c->ev_b[i]));
-                c->field_ms += ms;
-            }
-            c->field_launches += k;
-        }
-    }
-    if (c->shape.B > 0) {
-        CT_HIP(hipMemcpyAsync(taken1.data(), c->bt.ev_taken, sizeof(int64_t) * c->shape.B,
-                              hipMemcpyDeviceToHost, c->stream));
-        CT_HIP(hipStreamSynchronize(c->stream));
-    }
     int64_t done = 0;
-    for (int64_t b = 0; b < c->shape.B; ++b) done = std::max(done, taken1[b] - taken0[b]);
+    if (c->n_active > 0) {
+        CT_HIP(ct::launch_fill_i32((int32_t *)c->bt.call_steps, 2 * c->shape.B, 0, c->stream));
+        // one run takes every event to completion or to the step cap, unless
+        // the work queue filled up and some events were parked
+        for (;;) {
+            st = run_once(c, c->cfg, max_steps, 0, nullptr, timing);
+            if (st != CT_OK) return st;
+            if (!c->h_sched->exhausted.v) break;
+        }
+        c->n_active = c->h_sched->active;
+        done = c->h_sched->max_steps;
+    }
+    c->steps += done;
     if (steps_done) *steps_done = done;
     if (n_active) *n_active = c->n_active;
     c->step_wall_ms +=
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     if (c->n_active > 0)
         return fail(CT_EMAXSTEPS, "%lld holes still drifting after %lld steps",
-                    (long long)c->n_active, (long long)issued);
+                    (long long)c->n_active, (long long)done);
     return CT_OK;
 }
 
@@ -840,6 +821,7 @@ ct_status ct_collect(ct_ctx *c, int32_t *pixel_counts, double *xyz, int32_t *col
                      int64_t *event_steps, ct_run_stats *stats)
 {
     if (!c) return fail(CT_EINVAL, "ctx is NULL");
+    if (c->broken) return fail(CT_EDEVICE, "context unusable after a device error");
     if (!c->seeded) return fail(CT_ESTATE, "ct_collect before ct_seed_events");
     ct_status st = set_device(c);
     if (st != CT_OK) return st;
@@ -879,6 +861,7 @@ ct_status ct_collect(ct_ctx *c, int32_t *pixel_counts, double *xyz, int32_t *col
         r.targets_per_thread = c->cfg.kt;
         r.block_size = c->cfg.bs;
         r.chunk_len = c->cfg.chunk;
+        r.workgroups = c->grid;
         *stats = r;
     }
     return CT_OK;
@@ -887,6 +870,7 @@ ct_status ct_collect(ct_ctx *c, int32_t *pixel_counts, double *xyz, int32_t *col
 ct_status ct_field(ct_ctx *c, double *field)
 {
     if (!c) return fail(CT_EINVAL, "ctx is NULL");
+    if (c->broken) return fail(CT_EDEVICE, "context unusable after a device error");
     if (!c->seeded) return fail(CT_ESTATE, "ct_field before ct_seed_events");
     if (!field) return fail(CT_EINVAL, "field is NULL");
     ct_status st = set_device(c);
@@ -895,14 +879,8 @@ ct_status ct_field(ct_ctx *c, double *field)
     if (N == 0) return CT_OK;
     st = ensure_field_buf(c, N);
     if (st != CT_OK) return st;
-    // NaN everywhere, then the drifting carriers' fields
-    CT_HIP(ct::launch_fill_i32((int32_t *)c->field_buf, 6 * N, (int32_t)0xFFFFFFFF, c->stream));
-    ct::LaunchCfg cfg = c->cfg;
-    if (!(c->p.physics_flags & CT_REPULSION)) cfg.chunk = 0;
-    const int fp32 = c->p.precision == CT_FP32;
-    CT_HIP(ct::launch_plan(c->bt, cfg, c->stream));
-    CT_HIP(ct::launch_step(c->dp, c->bt, cfg, fp32, c->grid, 1, c->field_buf, c->stream));
-    CT_HIP(ct::launch_update(c->dp, c->bt, cfg, c->shape.n_max, 1, c->field_buf, c->stream));
+    st = field_into_buf(c, c->cfg, false);
+    if (st != CT_OK) return st;
     CT_HIP(hipMemcpyAsync(field, c->field_buf, sizeof(double) * 3 * N, hipMemcpyDeviceToHost,
                           c->stream));
     CT_HIP(hipStreamSynchronize(c->stream));
@@ -948,16 +926,11 @@ void ct_destroy(ct_ctx *c)
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->ws && !c->ws_bound) (void)hipFree(c->ws);
+    if (c->qbuf) (void)hipFree(c->qbuf);
     if (c->field_buf) (void)hipFree(c->field_buf);
-    if (c->part_buf) (void)hipFree(c->part_buf);
-    if (c->work_buf) (void)hipFree(c->work_buf);
-    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    if (c->h_pinned) (void)hipHostFree(c->h_pinned);
-    for (int i = 0; i < 64; ++i) {
-        if (c->ev_a[i]) (void)hipEventDestroy(c->ev_a[i]);
-        if (c->ev_b[i]) (void)hipEventDestroy(c->ev_b[i]);
-    }
+    if (c->h_sched) (void)hipHostFree(c->h_sched);
+    if (c->ev_a) (void)hipEventDestroy(c->ev_a);
+    if (c->ev_b) (void)hipEventDestroy(c->ev_b);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

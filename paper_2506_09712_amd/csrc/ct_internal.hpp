@@ -24,15 +24,40 @@ struct DevParams {
     uint32_t key0, key1;
 };
 
-// Device view of one batch.  Slots [off[b], off[b] + n_act[b]) of the
-// position arrays hold the drifting holes of event b, compacted and in
-// carrier order.
-// One work item of the step kernel: the target tile `tile` of event b
-// against its source chunk c of nsplit.
-struct Item {
-    int32_t b, tile, c, nsplit;
+// Most source chunks an event is split into; larger events get longer chunks.
+constexpr int kMaxChunks = 256;
+
+// One work item: target tile `tile` of event `e` (bs * kt targets) against
+// source chunk `chunk` of the same event, for the event's current step.
+struct QItem {
+    int32_t e, tile, chunk, pad;
 };
 
+// Control block of one run of the persistent step kernel.  Tickets index the
+// work queue; a ticket's item is valid once its sequence word equals the
+// run's generation.  Each counter that workgroups update or poll has a
+// 256-byte line of its own: atomics on one shared line serialise device-wide.
+struct alignas(256) Line {
+    uint32_t v;
+    uint32_t pad[63];
+};
+
+struct Sched {
+    Line head;       // next ticket to claim
+    Line tail;       // next ticket to reserve
+    Line done;       // events finished for this run (drained, at the step cap, or parked)
+    Line error;      // 1: the liveness guard expired; 2: the first step did not fit the queue
+    Line exhausted;  // 1: some event was parked because the queue was full
+    int64_t active;      // drifting holes (summary kernel)
+    int64_t max_steps;   // most steps any event took in this call (summary kernel)
+};
+
+// Completion counter of an event's step: one 64-byte line per event.
+constexpr int kEventLine = 16;  // int32 words
+
+// Device view of a batch.  Slots [off[b], off[b] + n_act[b]) of the position
+// arrays hold the drifting holes of event b, compacted and in carrier order;
+// slots [off[b], off[b + 1]) belong to event b for the whole run.
 struct DevBatch {
     int32_t n_events;
     int32_t n_total;
@@ -41,6 +66,7 @@ struct DevBatch {
     int32_t *n_act;         // [B] drifting holes
     int64_t *ev_step;       // [B] absolute step of the event
     int64_t *ev_taken;      // [B] steps taken since seeding
+    int64_t *call_steps;    // [B] steps taken in the current ct_step call
     double *ref;            // [B][4] reference point (centroid) for FP32 coordinates
     double *cx, *cy, *cz;   // [N] current positions (compacted)
     double *nx, *ny, *nz;   // [N] positions after the step (same slots)
@@ -51,43 +77,62 @@ struct DevBatch {
     int32_t *pix;           // [B][grid_n^2 + 1]
     uint64_t *pairs;        // [B] sum over steps of N_a (N_a - 1)
     uint64_t *hsteps;       // [B] sum over steps of N_a
-    int64_t *active;        // [1] drifting holes after the last compaction
-    double *part;           // [nsplit][3][N] partial fields of split events
-    int32_t part_chunks;    // chunks the partial buffer holds
-    Item *work;             // [work_cap] work list of the current step
-    int32_t work_cap;
-    int32_t *item_base;     // [B] first item of each event
-    int32_t *n_items;       // [1]
-    uint32_t *counter;      // [1] next item to take
     // seeding inputs
     const double *sigma;    // [B]
     const int32_t *dep_off; // [B + 1]
     const double *deposits; // [n_dep][3]
-    const int32_t *x_off;   // [B + 1] offsets into explicit positions (-1 rows: none)
+    const int32_t *x_off;   // [B + 1] offsets into explicit positions
     const double *xyz_in;   // [n_explicit][3]
     const int64_t *start;   // [B]
 };
 
+// Work queue and per-event scheduling state of the persistent step kernel,
+// sized for a batch and a launch configuration.
+struct DevQueue {
+    Sched *sc;
+    QItem *q;               // [cap]
+    uint32_t *seq;          // [cap]
+    uint32_t cap;
+    uint32_t gen;           // generation of the current run (never 0)
+    int32_t *tiles_left;    // [B * kEventLine] target tiles of the event's step not yet updated
+    int32_t *chunks_left;   // [sum of tiles] source chunks of a target tile not yet summed
+    const int32_t *tile_base;  // [B + 1] prefix of the most target tiles of each event
+    double *part;           // partial fields of split events
+    const int64_t *part_off;   // [B + 1] prefix of 3 * n0 * most chunks of each event
+};
+
 struct LaunchCfg {
     int kt;        // targets per thread
-    int bs;        // block size
-    int chunk;     // longest source chunk of one work item; an event with n holes is
-                   // split into ceil(n / chunk) chunks of equal length (0: no split)
+    int bs;        // block size = sources per LDS tile
+    int chunk;     // source chunk length (a multiple of bs; events longer than this are split)
 };
 
 // Kernel launchers (ct_kernels.hip).  All return the launch status.
 hipError_t launch_seed(const DevParams &dp, const DevBatch &bt, hipStream_t s);
-hipError_t launch_compact(const DevParams &dp, const DevBatch &bt, int count_step, hipStream_t s);
-hipError_t launch_plan(const DevBatch &bt, const LaunchCfg &cfg, hipStream_t s);
-hipError_t launch_step(const DevParams &dp, const DevBatch &bt, const LaunchCfg &cfg, int fp32,
-                       int grid, int field_only, double *field_out, hipStream_t s);
-int step_occupancy(const LaunchCfg &cfg, int fp32);
+hipError_t launch_compact(const DevParams &dp, const DevBatch &bt, hipStream_t s);
+hipError_t launch_init(const DevBatch &bt, const DevQueue &dq, const LaunchCfg &cfg,
+                       int64_t max_steps, int field_only, int repulsion, hipStream_t s);
+hipError_t launch_run(const DevParams &dp, const DevBatch &bt, const DevQueue &dq,
+                      const LaunchCfg &cfg, int fp32, int grid, int64_t max_steps, int field_only,
+                      double *field_out, hipStream_t s);
+hipError_t launch_summary(const DevBatch &bt, Sched *sc, hipStream_t s);
+int run_occupancy(const LaunchCfg &cfg, int fp32);
 bool launch_supported(int kt, int bs);
-hipError_t launch_update(const DevParams &dp, const DevBatch &bt, const LaunchCfg &cfg, int n_max,
-                         int field_only, double *field_out, hipStream_t s);
 hipError_t launch_scatter_alive(const DevBatch &bt, int n_max, hipStream_t s);
 hipError_t launch_philox(const DevParams &dp, const uint32_t *ctr, int64_t n, uint32_t *words,
                          double *normals, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+
+// Source chunk length and count of an event of n drifting holes: chunks of
+// `chunk` sources (a multiple of bs), lengthened to whole tiles so that no
+// event has more than kMaxChunks of them.  Depends on n and the launch only,
+// so the grouping of the field sum is a function of the event alone.
+__host__ __device__ inline void event_chunks(int n, int bs, int chunk, int &len, int &count)
+{
+    const int min_len = ((n + kMaxChunks - 1) / kMaxChunks + bs - 1) / bs * bs;
+    len = chunk > min_len ? chunk : min_len;
+    if (len < bs) len = bs;
+    count = n > 0 ? (n + len - 1) / len : 0;
+}
 
 }  // namespace ct

@@ -1,18 +1,26 @@
 // HIP kernels of the brute-force charge-transport Monte Carlo for gfx950
 // (Xie et al., arXiv:2506.09712, Sec. 2.1 and Appendix A, Algorithm 1).
 //
-// One time step of a batch is three launches on one stream:
-//   k_step     per (event, target tile, source chunk) workgroup: the all-pairs
-//              repulsion field of Eq. 4 over the event's drifting holes, with
-//              source tiles staged in LDS and one thread per KT targets; for
-//              unsplit events the update of Eqs. 3, 5 and 6 (drift field,
-//              mobility, diffusion, collection, pixel count) runs in the same
-//              kernel;
-//   k_update   for events whose sources were split over several workgroups:
-//              sums the partial fields in chunk order and applies the update;
-//   k_compact  one workgroup per event: keeps the holes still drifting, in
-//              carrier order (wave ballot + mbcnt prefix, workgroup scan),
-//              recomputes the event centroid and counts the step.
+// Events never interact, so an event's step t + 1 needs only its own step t.
+// A ct_step call is therefore one persistent kernel (k_run) fed by a device
+// work queue, with no device-wide barrier between steps:
+//   k_init     queues the first step of every event still drifting: one item
+//              per (target tile, source chunk) of the event;
+//   k_run      a resident grid of workgroups; each claims the next ticket of
+//              the queue, computes the all-pairs repulsion field of Eq. 4 of
+//              its target tile over its source chunk (source tiles staged in
+//              LDS, one thread per KT targets), and writes the partial field.
+//              The workgroup that completes the last chunk of a target tile
+//              sums the partials in chunk order and applies the update of
+//              Eqs. 3, 5 and 6 (drift field, mobility, diffusion, collection,
+//              pixel count); the one that completes the event's last tile
+//              compacts the event (holes still drifting, in carrier order),
+//              recomputes its centroid, counts the step and queues the
+//              event's next step;
+//   k_summary  drifting holes and steps taken, for the host.
+// The split of an event into tiles and chunks depends only on its own hole
+// count, and partials are always summed in chunk order, so the result of an
+// event does not depend on the rest of the batch or on scheduling.
 #include <math.h>
 
 #include "ct_internal.hpp"
@@ -23,7 +31,6 @@ namespace {
 
 constexpr uint32_t kDomainDiffusion = 0u;
 constexpr uint32_t kDomainCloud = 1u;
-constexpr int kCompactThreads = 1024;
 
 // ------------------------------------------------------------------ Philox
 
@@ -66,6 +73,61 @@ __device__ void normals3(const DevParams &dp, Ctr ctr, double n[3])
     n[0] = ra * c1;
     n[1] = ra * s1;
     n[2] = rb * cospi(2.0 * u3);
+}
+
+// ------------------------------------------------------------ memory order
+
+// Publication between workgroups of one run.  Data that other workgroups
+// read later in the same run is stored with agent-scope relaxed atomic
+// stores, which go to device-coherent memory instead of staying dirty in the
+// L2 of this XCD.  After a workgroup barrier (all waves of a workgroup share
+// one CU and its in-order vector memory path), thread 0 publishes with a
+// release operation on a completion counter or flag; its L2 write-back then
+// has almost nothing to do.  The observing thread reads the flag, executes an
+// acquire fence (invalidating stale cache lines), and a workgroup barrier
+// orders the rest of its workgroup's loads after it.
+__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+__device__ __forceinline__ void st_dev(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_dev(int32_t *p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_dev(int64_t *p, int64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t ld_relaxed(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_relaxed(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t add_relaxed(uint32_t *p, uint32_t v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Decrement of a completion counter (thread 0, after a workgroup barrier):
+// releases the workgroup's results; the caller that takes the counter to
+// zero also acquires everyone else's.
+__device__ __forceinline__ bool dec_is_last(int32_t *p)
+{
+    const int32_t left = __hip_atomic_fetch_add(p, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (left != 1) return false;
+    fence_acquire();
+    return true;
 }
 
 // ------------------------------------------------------------------ physics
@@ -118,9 +180,9 @@ __device__ void advance(const DevParams &dp, const DevBatch &bt, int b, int slot
     const double y1 = y + mu * ey * dp.dt + hop * g[1];
     double z1 = z + mu * ez * dp.dt + hop * g[2];
     if (z1 > dp.H) z1 = 2.0 * dp.H - z1;  // mirror at the entrance side
-    bt.nx[slot] = x1;
-    bt.ny[slot] = y1;
-    bt.nz[slot] = z1;
+    st_dev(&bt.nx[slot], x1);
+    st_dev(&bt.ny[slot], y1);
+    st_dev(&bt.nz[slot], z1);
     if (z1 <= 0.0) collect(dp, bt, b, carrier, x1, y1, z1, step + 1);
 }
 
@@ -208,298 +270,27 @@ __device__ __forceinline__ void pair_f64(const D4 &s, double s2, const double (&
     }
 }
 
-// ------------------------------------------------------------------ kernels
+// ------------------------------------------------------------ compaction
 
-// Sources of an event split into nsplit chunks: equal lengths rounded up to
-// whole LDS tiles, so every chunk boundary is also a tile boundary.
-__device__ __forceinline__ int chunk_length(int n, int nsplit, int bs)
+// Holes of event b with z > 0 after the step survive; they are packed to the
+// front of the event's slots in carrier order by the NT threads of one
+// workgroup.  Each wave ranks its survivors with a 64-bit ballot and mbcnt,
+// the workgroup adds the wave totals; carrier indices are compacted in place
+// (every read of a chunk precedes the barrier, every write follows it and
+// lands at or below it).  Thread 0 stores the new count and centroid (summed
+// in a fixed order) and, for a step, counts it.  Returns the survivors (in
+// every thread); ends with a barrier.
+template <int NT>
+__device__ int compact_event(const DevBatch &bt, int b, int count_step, int *wcount, double *wsum)
 {
-    if (nsplit <= 1) return n;
-    const int per = (n + nsplit - 1) / nsplit;
-    return (per + bs - 1) / bs * bs;
-}
-
-// Pair work of one item.  Thread t owns targets tile*BS*KT + m*BS + t
-// (m < KT); the workgroup stages the sources in LDS tiles of BS.  Waves whose
-// targets all lie past the event's end only help staging.  For unsplit events
-// the update follows in the same kernel; otherwise the raw partial sum is
-// stored for k_update.
-template <int KT, int BS, bool F32>
-__device__ void run_item(const DevParams &dp, const DevBatch &bt, const Item it, int chunk,
-                         int field_only, double *field_out, void *lds)
-{
-    const int b = it.b;
-    const int n = bt.n_act[b];
-    const int t0 = it.tile * (BS * KT);
-    const int clen = chunk_length(n, it.nsplit, BS);
-    const int sb = it.c * clen;
-    const int se = min(n, sb + clen);
-    const int base = bt.off[b];
-    const int tid = threadIdx.x;
-    const bool wave_has_targets = t0 + (tid & ~63) < n;
-
-    double ex[KT], ey[KT], ez[KT];
-#pragma unroll
-    for (int m = 0; m < KT; ++m) ex[m] = ey[m] = ez[m] = 0.0;
-
-    if (dp.flags & 1u) {
-        if constexpr (F32) {
-            float4 *tile = static_cast<float4 *>(lds);
-            const double rx = bt.ref[4 * b + 0], ry = bt.ref[4 * b + 1], rz = bt.ref[4 * b + 2];
-            float tx[KT], ty[KT], tz[KT];
-#pragma unroll
-            for (int m = 0; m < KT; ++m) {
-                const int s = t0 + m * BS + tid;
-                if (s < n) {
-                    tx[m] = (float)(bt.cx[base + s] - rx);
-                    ty[m] = (float)(bt.cy[base + s] - ry);
-                    tz[m] = (float)(bt.cz[base + s] - rz);
-                } else {
-                    tx[m] = ty[m] = tz[m] = 0.0f;
-                }
-            }
-            for (int s0 = sb; s0 < se; s0 += BS) {
-                __syncthreads();
-                const int j = s0 + tid;
-                float4 v = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
-                if (j < se)
-                    v = make_float4((float)(bt.cx[base + j] - rx), (float)(bt.cy[base + j] - ry),
-                                    (float)(bt.cz[base + j] - rz), 0.0f);
-                tile[tid] = v;
-                __syncthreads();
-                if (!wave_has_targets) continue;
-                const int cnt = (min(BS, se - s0) + CT_PAIR_UNROLL - 1) / CT_PAIR_UNROLL * CT_PAIR_UNROLL;
-                float ax[KT], ay[KT], az[KT];
-#pragma unroll
-                for (int m = 0; m < KT; ++m) ax[m] = ay[m] = az[m] = 0.0f;
-                pairs_f32<KT>(tile, cnt, dp.s2f, tx, ty, tz, ax, ay, az);
-#pragma unroll
-                for (int m = 0; m < KT; ++m) {  // fold the tile's FP32 partial into FP64
-                    ex[m] += (double)ax[m];
-                    ey[m] += (double)ay[m];
-                    ez[m] += (double)az[m];
-                }
-            }
-        } else {
-            D4 *tile = static_cast<D4 *>(lds);
-            double tx[KT], ty[KT], tz[KT];
-#pragma unroll
-            for (int m = 0; m < KT; ++m) {
-                const int s = t0 + m * BS + tid;
-                if (s < n) {
-                    tx[m] = bt.cx[base + s];
-                    ty[m] = bt.cy[base + s];
-                    tz[m] = bt.cz[base + s];
-                } else {
-                    tx[m] = ty[m] = tz[m] = 0.0;
-                }
-            }
-            const double s2 = dp.s2;
-            for (int s0 = sb; s0 < se; s0 += BS) {
-                __syncthreads();
-                const int j = s0 + tid;
-                if (j < se) tile[tid] = D4{bt.cx[base + j], bt.cy[base + j], bt.cz[base + j], 0.0};
-                __syncthreads();
-                if (!wave_has_targets) continue;
-                const int cnt = min(BS, se - s0);
-                const int cnt4 = cnt & ~3;
-                for (int j0 = 0; j0 < cnt4; j0 += 4) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        pair_f64<KT>(tile[j0 + u], s2, tx, ty, tz, ex, ey, ez);
-                }
-                for (int jj = cnt4; jj < cnt; ++jj) pair_f64<KT>(tile[jj], s2, tx, ty, tz, ex, ey, ez);
-            }
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < KT; ++m) {
-        const int s = t0 + m * BS + tid;
-        if (s >= n) continue;
-        if (it.nsplit == 1) {
-            field_or_advance(dp, bt, b, base + s, dp.K * ex[m], dp.K * ey[m], dp.K * ez[m],
-                             field_only, field_out);
-        } else {
-            const int64_t N = bt.n_total;
-            bt.part[(3 * (int64_t)it.c + 0) * N + base + s] = ex[m];
-            bt.part[(3 * (int64_t)it.c + 1) * N + base + s] = ey[m];
-            bt.part[(3 * (int64_t)it.c + 2) * N + base + s] = ez[m];
-        }
-    }
-}
-
-// Persistent step kernel: a fixed grid sized to the resident capacity of the
-// device; each workgroup takes the next item of the step's work list with one
-// atomic until the list is exhausted, so every workgroup exits.
-// Resident waves per SIMD the pair kernels are compiled for: the pair loop
-// needs few registers, the update epilogue many; capping registers so that 8
-// waves share each SIMD (FP32) measured 5-7% faster than the unconstrained
-// allocation (84 registers, 5 waves).
-#ifndef CT_F32_WAVES_PER_EU
-#define CT_F32_WAVES_PER_EU 8
-#endif
-#ifndef CT_F64_WAVES_PER_EU
-#define CT_F64_WAVES_PER_EU 4
-#endif
-
-// Persistent step kernel: a fixed grid sized to the resident capacity of the
-// device; each workgroup takes the next item of the step's work list with one
-// atomic until the list is exhausted, so every workgroup exits.
-template <int KT, int BS, bool F32>
-__device__ __forceinline__ void step_loop(const DevParams &dp, const DevBatch &bt, int chunk,
-                                          int field_only, double *field_out, void *lds)
-{
-    __shared__ int s_item;
-    const int n_items = *bt.n_items;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(bt.counter, 1u);
-        __syncthreads();
-        const int i = s_item;
-        if (i >= n_items) break;
-        run_item<KT, BS, F32>(dp, bt, bt.work[i], chunk, field_only, field_out, lds);
-    }
-}
-
-template <int KT, int BS>
-__global__ __launch_bounds__(BS)
-__attribute__((amdgpu_waves_per_eu(KT == 1 ? CT_F32_WAVES_PER_EU : 5)))
-void k_step_f32(DevParams dp, DevBatch bt, int chunk, int field_only, double *field_out)
-{
-    __shared__ float4 lds[BS];
-    step_loop<KT, BS, true>(dp, bt, chunk, field_only, field_out, lds);
-}
-
-template <int KT, int BS>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(CT_F64_WAVES_PER_EU)))
-void k_step_f64(DevParams dp, DevBatch bt, int chunk, int field_only, double *field_out)
-{
-    __shared__ D4 lds[BS];
-    step_loop<KT, BS, false>(dp, bt, chunk, field_only, field_out, lds);
-}
-
-// Work list of one step (one workgroup of 1024): per event ceil(n/T) target
-// tiles times ceil(n/chunk) source chunks, events in order, items of an event
-// contiguous.  Also resets the item counter and the drifting-hole total.
-// Up to kPlanLds events keep their item offsets in LDS and every thread emits
-// items located by binary search; larger batches emit one event per wave.
-constexpr int kPlanLds = 4096;
-
-__global__ __launch_bounds__(1024) void k_plan(DevBatch bt, int T, int chunk)
-{
-    __shared__ int wtot[16];
-    __shared__ int carry;
-    __shared__ int s_base[kPlanLds + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int B = bt.n_events;
-    const bool in_lds = B <= kPlanLds;
-    if (tid == 0) carry = 0;
-    __syncthreads();
-    for (int e0 = 0; e0 < B; e0 += 1024) {
-        const int e = e0 + tid;
-        int items = 0;
-        if (e < B) {
-            const int n = bt.n_act[e];
-            if (n > 0) items = ((n + T - 1) / T) * (chunk > 0 ? (n + chunk - 1) / chunk : 1);
-        }
-        int v = items;  // inclusive scan within the wave
-        for (int o = 1; o < 64; o <<= 1) {
-            const int t = __shfl_up(v, o);
-            if (lane >= o) v += t;
-        }
-        if (lane == 63) wtot[wave] = v;
-        __syncthreads();
-        int before = 0, total = 0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            before += q < wave ? wtot[q] : 0;
-            total += wtot[q];
-        }
-        if (e < B) {
-            const int base = carry + before + v - items;
-            if (in_lds) s_base[e] = base;
-            else bt.item_base[e] = base;
-        }
-        __syncthreads();
-        if (tid == 0) carry += total;
-        __syncthreads();
-    }
-    const int total = min(carry, bt.work_cap);
-    if (in_lds) {
-        if (tid == 0) s_base[B] = carry;
-        __syncthreads();
-        for (int i = tid; i < total; i += 1024) {
-            int lo = 0, hi = B;  // s_base[lo] <= i < s_base[hi]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (s_base[mid] <= i) lo = mid;
-                else hi = mid;
-            }
-            const int n = bt.n_act[lo];
-            const int ns = chunk > 0 ? (n + chunk - 1) / chunk : 1;
-            const int k = i - s_base[lo];
-            bt.work[i] = Item{lo, k / ns, k % ns, ns};
-        }
-    } else {
-        for (int e = wave; e < B; e += 16) {
-            const int n = bt.n_act[e];
-            if (n <= 0) continue;
-            const int ns = chunk > 0 ? (n + chunk - 1) / chunk : 1;
-            const int items = ((n + T - 1) / T) * ns;
-            const int base = bt.item_base[e];
-            for (int i = lane; i < items; i += 64)
-                if (base + i < bt.work_cap) bt.work[base + i] = Item{e, i / ns, i % ns, ns};
-        }
-    }
-    if (tid == 0) {
-        *bt.n_items = total;
-        *bt.counter = 0u;
-        bt.active[0] = 0;
-    }
-}
-
-// Events split over several source chunks: sum the partial fields in chunk
-// order, then update.  Grid: (slot tiles of 256, events).
-__global__ __launch_bounds__(256) void k_update(DevParams dp, DevBatch bt, int chunk,
-                                                int field_only, double *field_out)
-{
-    const int b = blockIdx.y;
-    const int n = bt.n_act[b];
-    const int nsplit = chunk > 0 ? (n + chunk - 1) / chunk : 1;
-    if (nsplit <= 1) return;
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= n) return;
-    const int slot = bt.off[b] + s;
-    const int64_t N = bt.n_total;
-    double ex = 0.0, ey = 0.0, ez = 0.0;
-    for (int c = 0; c < nsplit; ++c) {
-        ex += bt.part[(3 * (int64_t)c + 0) * N + slot];
-        ey += bt.part[(3 * (int64_t)c + 1) * N + slot];
-        ez += bt.part[(3 * (int64_t)c + 2) * N + slot];
-    }
-    field_or_advance(dp, bt, b, slot, dp.K * ex, dp.K * ey, dp.K * ez, field_only, field_out);
-}
-
-// One workgroup per event.  Holes with z > 0 after the step survive; they
-// are packed to the front of the event's slots in carrier order.  Each wave
-// ranks its survivors with a 64-bit ballot and mbcnt, the workgroup adds the
-// wave totals; carrier indices are compacted in place (every read of a chunk
-// precedes the barrier, every write follows it and lands at or below it).
-__global__ __launch_bounds__(kCompactThreads) void k_compact(DevParams dp, DevBatch bt,
-                                                             int count_step)
-{
-    (void)dp;
-    constexpr int W = kCompactThreads / 64;
-    __shared__ int wcount[W];
-    __shared__ double wsum[3][W];
-    const int b = blockIdx.x;
+    constexpr int W = NT / 64;
     const int n = bt.n_act[b];
     const int base = bt.off[b];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     int kept = 0;
     double sx = 0.0, sy = 0.0, sz = 0.0;
-    for (int c0 = 0; c0 < n; c0 += kCompactThreads) {
+    for (int c0 = 0; c0 < n; c0 += NT) {
         const int i = c0 + tid;
         bool alive = false;
         double x = 0.0, y = 0.0, z = 0.0;
@@ -527,10 +318,10 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(DevParams dp, DevBa
         }
         if (alive) {
             const int d = base + kept + before + rank;
-            bt.cx[d] = x;
-            bt.cy[d] = y;
-            bt.cz[d] = z;
-            bt.idx[d] = k;
+            st_dev(&bt.cx[d], x);
+            st_dev(&bt.cy[d], y);
+            st_dev(&bt.cz[d], z);
+            st_dev(&bt.idx[d], k);
             sx += x;
             sy += y;
             sz += z;
@@ -538,39 +329,445 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(DevParams dp, DevBa
         kept += total;
         __syncthreads();
     }
-    // fixed-order reduction of the survivors' coordinate sums (deterministic)
     for (int o = 32; o > 0; o >>= 1) {
         sx += __shfl_down(sx, o);
         sy += __shfl_down(sy, o);
         sz += __shfl_down(sz, o);
     }
     if (lane == 0) {
-        wsum[0][wave] = sx;
-        wsum[1][wave] = sy;
-        wsum[2][wave] = sz;
+        wsum[0 * W + wave] = sx;
+        wsum[1 * W + wave] = sy;
+        wsum[2 * W + wave] = sz;
     }
     __syncthreads();
     if (tid == 0) {
         double X = 0.0, Y = 0.0, Z = 0.0;
         for (int q = 0; q < W; ++q) {
-            X += wsum[0][q];
-            Y += wsum[1][q];
-            Z += wsum[2][q];
+            X += wsum[0 * W + q];
+            Y += wsum[1 * W + q];
+            Z += wsum[2 * W + q];
         }
         if (kept > 0) {
-            bt.ref[4 * b + 0] = X / kept;
-            bt.ref[4 * b + 1] = Y / kept;
-            bt.ref[4 * b + 2] = Z / kept;
+            st_dev(&bt.ref[4 * b + 0], X / kept);
+            st_dev(&bt.ref[4 * b + 1], Y / kept);
+            st_dev(&bt.ref[4 * b + 2], Z / kept);
         }
-        bt.n_act[b] = kept;
+        st_dev(&bt.n_act[b], kept);
         if (count_step && n > 0) {
             bt.pairs[b] += (uint64_t)n * (uint64_t)(n - 1);
             bt.hsteps[b] += (uint64_t)n;
-            bt.ev_step[b] += 1;
-            bt.ev_taken[b] += 1;
+            st_dev(&bt.ev_step[b], bt.ev_step[b] + 1);
+            st_dev(&bt.ev_taken[b], bt.ev_taken[b] + 1);
+            st_dev(&bt.call_steps[b], bt.call_steps[b] + 1);
         }
-        if (kept > 0) atomicAdd((unsigned long long *)bt.active, (unsigned long long)kept);
     }
+    __syncthreads();
+    return kept;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// Resident waves per SIMD the run kernels are compiled for: the pair loop
+// needs few registers, the update and compaction many; capping registers so
+// that 8 waves share each SIMD (FP32, one target per thread) measured 5-7%
+// faster than the unconstrained allocation (5 waves).
+#ifndef CT_F32_WAVES_PER_EU
+#define CT_F32_WAVES_PER_EU 8
+#endif
+#ifndef CT_F64_WAVES_PER_EU
+#define CT_F64_WAVES_PER_EU 4
+#endif
+
+// Longest time (seconds) a workgroup waits while no event step is queued and
+// no event finishes anywhere before it gives up and reports an error; the
+// longest legitimate gap is one step of the largest event (well under a
+// second for a million holes).
+constexpr double kIdleSeconds = 10.0;
+
+struct RunArgs {
+    int chunk;             // source chunk length
+    int field_only;        // 1: write the field of every drifting hole, no update
+    int64_t max_steps;     // steps per event in this call
+    uint64_t idle_ticks;   // kIdleSeconds in wall-clock ticks
+    double *field_out;     // [N][3] by carrier (field_only)
+};
+
+// Claim the next ticket and wait until its item is published.  Thread 0
+// only.  Returns 1 with the item, or 0 when the run is over: the ticket lies
+// past the queue, every event is finished (then no published ticket is left
+// unclaimed), or another workgroup reported an error.  Liveness: a ticket is
+// only ever held by a running workgroup and publishing never waits, so while
+// some event is unfinished, some workgroup holds one of its items or is about
+// to publish its next step.  The wait polls only the ticket's own sequence
+// word, backing off, and looks at the shared counters every 16th poll; if
+// neither an event step was queued nor an event finished for idle_ticks it
+// sets the error flag instead of spinning on.
+__device__ int claim(const DevQueue &dq, uint32_t n_events, uint64_t idle_ticks, QItem &out)
+{
+    Sched *sc = dq.sc;
+    const uint32_t t = add_relaxed(&sc->head.v, 1u);
+    if (t >= dq.cap) return 0;
+    uint32_t seen_tail = 0, seen_done = 0;
+    uint64_t since = wall_clock64();
+    for (uint32_t it = 0;; ++it) {
+        if (ld_relaxed(&dq.seq[t]) == dq.gen) break;
+        if ((it & 15u) == 15u) {
+            const uint32_t dn = ld_relaxed(&sc->done.v);
+            if (dn >= n_events || ld_relaxed(&sc->error.v)) return 0;
+            const uint32_t tl = ld_relaxed(&sc->tail.v);
+            const uint64_t now = wall_clock64();
+            if (tl != seen_tail || dn != seen_done) {
+                seen_tail = tl;
+                seen_done = dn;
+                since = now;
+            } else if (now - since > idle_ticks) {
+                st_relaxed(&sc->error.v, 1u);
+                return 0;
+            }
+        }
+        if (it < 64) __builtin_amdgcn_s_sleep(2);
+        else if (it < 1024) __builtin_amdgcn_s_sleep(16);
+        else __builtin_amdgcn_s_sleep(127);
+    }
+    fence_acquire();
+    out = dq.q[t];
+    return 1;
+}
+
+template <int KT, int BS, bool F32>
+__device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue &dq,
+                         const RunArgs &ra, void *lds)
+{
+    constexpr int T = KT * BS;
+    constexpr int W = BS / 64;
+    __shared__ QItem s_item;
+    __shared__ int s_go;
+    __shared__ int s_wcount[W];
+    __shared__ double s_wsum[3 * W];
+    __shared__ int s_items, s_tiles, s_chunks;
+    __shared__ uint32_t s_t0;
+    const int tid = threadIdx.x;
+    Sched *sc = dq.sc;
+    const uint32_t n_events = (uint32_t)bt.n_events;
+    const bool repulsion = (dp.flags & 1u) != 0;
+
+    for (;;) {
+        __syncthreads();  // LDS of the previous item is free
+        if (tid == 0) {
+            QItem it{};
+            s_go = claim(dq, n_events, ra.idle_ticks, it);
+            s_item = it;
+        }
+        __syncthreads();
+        if (!s_go) break;
+        const QItem it = s_item;
+        const int b = it.e;
+        const int n = bt.n_act[b];
+        const int base = bt.off[b];
+        const int n0 = bt.off[b + 1] - base;
+        int len = n, chunks = 1;
+        if (repulsion) event_chunks(n, BS, ra.chunk, len, chunks);
+        const int t0 = it.tile * T;
+        const int sb = it.chunk * len;
+        const int se = min(n, sb + len);
+        const bool wave_has_targets = t0 + (tid & ~63) < n;
+
+        double ex[KT], ey[KT], ez[KT];
+#pragma unroll
+        for (int m = 0; m < KT; ++m) ex[m] = ey[m] = ez[m] = 0.0;
+
+        if (repulsion) {
+            if constexpr (F32) {
+                float4 *tile = static_cast<float4 *>(lds);
+                const double rx = bt.ref[4 * b + 0], ry = bt.ref[4 * b + 1], rz = bt.ref[4 * b + 2];
+                float tx[KT], ty[KT], tz[KT];
+#pragma unroll
+                for (int m = 0; m < KT; ++m) {
+                    const int s = t0 + m * BS + tid;
+                    if (s < n) {
+                        tx[m] = (float)(bt.cx[base + s] - rx);
+                        ty[m] = (float)(bt.cy[base + s] - ry);
+                        tz[m] = (float)(bt.cz[base + s] - rz);
+                    } else {
+                        tx[m] = ty[m] = tz[m] = 0.0f;
+                    }
+                }
+                for (int s0 = sb; s0 < se; s0 += BS) {
+                    __syncthreads();
+                    const int j = s0 + tid;
+                    float4 v = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
+                    if (j < se)
+                        v = make_float4((float)(bt.cx[base + j] - rx), (float)(bt.cy[base + j] - ry),
+                                        (float)(bt.cz[base + j] - rz), 0.0f);
+                    tile[tid] = v;
+                    __syncthreads();
+                    if (!wave_has_targets) continue;
+                    const int cnt = (min(BS, se - s0) + CT_PAIR_UNROLL - 1) / CT_PAIR_UNROLL * CT_PAIR_UNROLL;
+                    float ax[KT], ay[KT], az[KT];
+#pragma unroll
+                    for (int m = 0; m < KT; ++m) ax[m] = ay[m] = az[m] = 0.0f;
+                    pairs_f32<KT>(tile, cnt, dp.s2f, tx, ty, tz, ax, ay, az);
+#pragma unroll
+                    for (int m = 0; m < KT; ++m) {  // fold the tile's FP32 partial into FP64
+                        ex[m] += (double)ax[m];
+                        ey[m] += (double)ay[m];
+                        ez[m] += (double)az[m];
+                    }
+                }
+            } else {
+                D4 *tile = static_cast<D4 *>(lds);
+                double tx[KT], ty[KT], tz[KT];
+#pragma unroll
+                for (int m = 0; m < KT; ++m) {
+                    const int s = t0 + m * BS + tid;
+                    if (s < n) {
+                        tx[m] = bt.cx[base + s];
+                        ty[m] = bt.cy[base + s];
+                        tz[m] = bt.cz[base + s];
+                    } else {
+                        tx[m] = ty[m] = tz[m] = 0.0;
+                    }
+                }
+                const double s2 = dp.s2;
+                for (int s0 = sb; s0 < se; s0 += BS) {
+                    __syncthreads();
+                    const int j = s0 + tid;
+                    if (j < se) tile[tid] = D4{bt.cx[base + j], bt.cy[base + j], bt.cz[base + j], 0.0};
+                    __syncthreads();
+                    if (!wave_has_targets) continue;
+                    const int cnt = min(BS, se - s0);
+                    const int cnt4 = cnt & ~3;
+                    for (int j0 = 0; j0 < cnt4; j0 += 4) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            pair_f64<KT>(tile[j0 + u], s2, tx, ty, tz, ex, ey, ez);
+                    }
+                    for (int jj = cnt4; jj < cnt; ++jj) pair_f64<KT>(tile[jj], s2, tx, ty, tz, ex, ey, ez);
+                }
+            }
+        }
+
+        if (chunks > 1) {
+            // this chunk's partial field; the tile's last chunk sums them all
+            const int64_t po = dq.part_off[b] + 3 * (int64_t)it.chunk * n0;
+#pragma unroll
+            for (int m = 0; m < KT; ++m) {
+                const int s = t0 + m * BS + tid;
+                if (s < n) {
+                    st_dev(&dq.part[po + s], ex[m]);
+                    st_dev(&dq.part[po + n0 + s], ey[m]);
+                    st_dev(&dq.part[po + 2 * n0 + s], ez[m]);
+                }
+            }
+            __syncthreads();
+            if (tid == 0) s_go = dec_is_last(&dq.chunks_left[dq.tile_base[b] + it.tile]);
+            __syncthreads();
+            if (!s_go) continue;
+#pragma unroll
+            for (int m = 0; m < KT; ++m) {
+                const int s = t0 + m * BS + tid;
+                ex[m] = ey[m] = ez[m] = 0.0;
+                if (s >= n) continue;
+                for (int c = 0; c < chunks; ++c) {
+                    const int64_t o = dq.part_off[b] + 3 * (int64_t)c * n0 + s;
+                    ex[m] += dq.part[o];
+                    ey[m] += dq.part[o + n0];
+                    ez[m] += dq.part[o + 2 * n0];
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < KT; ++m) {
+            const int s = t0 + m * BS + tid;
+            if (s < n)
+                field_or_advance(dp, bt, b, base + s, dp.K * ex[m], dp.K * ey[m], dp.K * ez[m],
+                                 ra.field_only, ra.field_out);
+        }
+        __syncthreads();
+        if (tid == 0) s_go = dec_is_last(&dq.tiles_left[b * kEventLine]);
+        __syncthreads();
+        if (!s_go) continue;
+
+        // every tile of the event's step is updated
+        if (ra.field_only) {
+            if (tid == 0) add_relaxed(&sc->done.v, 1u);
+            continue;
+        }
+        const int kept = compact_event<BS>(bt, b, 1, s_wcount, s_wsum);
+        if (tid == 0) {
+            int items = 0, tiles = 0, nchunk = 1;
+            uint32_t t0q = 0;
+            if (kept > 0 && bt.call_steps[b] < ra.max_steps) {
+                tiles = (kept + T - 1) / T;
+                int l2 = kept;
+                if (repulsion) event_chunks(kept, BS, ra.chunk, l2, nchunk);
+                items = tiles * nchunk;
+                t0q = add_relaxed(&sc->tail.v, (uint32_t)items);
+                if ((uint64_t)t0q + (uint64_t)items > (uint64_t)dq.cap) {
+                    st_relaxed(&sc->exhausted.v, 1u);  // parked; the host runs again
+                    items = 0;
+                }
+            }
+            if (items == 0) add_relaxed(&sc->done.v, 1u);
+            s_items = items;
+            s_tiles = tiles;
+            s_chunks = nchunk;
+            s_t0 = t0q;
+        }
+        __syncthreads();
+        const int items = s_items;
+        if (items > 0) {
+            const int tiles = s_tiles, nchunk = s_chunks;
+            const uint32_t t0q = s_t0;
+            const int tb = dq.tile_base[b];
+            for (int j = tid; j < tiles; j += BS) st_dev(&dq.chunks_left[tb + j], nchunk);
+            if (tid == 0) st_dev(&dq.tiles_left[b * kEventLine], tiles);
+            for (int i = tid; i < items; i += BS) {
+                int32_t *w = reinterpret_cast<int32_t *>(dq.q + t0q + i);
+                st_dev(w, b);
+                st_dev(w + 1, i / nchunk);
+                st_dev(w + 2, i % nchunk);
+            }
+            __syncthreads();
+            fence_release();
+            for (int i = tid; i < items; i += BS) st_relaxed(&dq.seq[t0q + i], dq.gen);
+        }
+    }
+}
+
+template <int KT, int BS>
+__global__ __launch_bounds__(BS)
+__attribute__((amdgpu_waves_per_eu(KT == 1 ? CT_F32_WAVES_PER_EU : (KT == 2 ? 5 : 4))))
+void k_run_f32(DevParams dp, DevBatch bt, DevQueue dq, RunArgs ra)
+{
+    __shared__ float4 lds[BS];
+    run_loop<KT, BS, true>(dp, bt, dq, ra, lds);
+}
+
+template <int KT, int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(CT_F64_WAVES_PER_EU)))
+void k_run_f64(DevParams dp, DevBatch bt, DevQueue dq, RunArgs ra)
+{
+    __shared__ D4 lds[BS];
+    run_loop<KT, BS, false>(dp, bt, dq, ra, lds);
+}
+
+// First step of every event still drifting (and, for a field evaluation,
+// with no step cap): its items, tickets in event order, and its completion
+// counters; resets the run's control block.  One workgroup of 1024; events
+// in blocks of 1024, each wave emitting the items of every 16th event.
+__global__ __launch_bounds__(1024) void k_init(DevBatch bt, DevQueue dq, int T, int bs, int chunk,
+                                               int64_t max_steps, int field_only, int repulsion)
+{
+    __shared__ int wtot[16];
+    __shared__ uint32_t s_base[1024];
+    __shared__ int s_nitems[1024], s_nchunk[1024];
+    __shared__ uint32_t carry, n_done;
+    __shared__ int overflow;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int B = bt.n_events;
+    if (tid == 0) {
+        carry = 0;
+        n_done = 0;
+        overflow = 0;
+    }
+    __syncthreads();
+    for (int e0 = 0; e0 < B; e0 += 1024) {
+        const int e = e0 + tid;
+        int items = 0, nchunk = 1;
+        if (e < B) {
+            const int n = bt.n_act[e];
+            if (n > 0 && (field_only || bt.call_steps[e] < max_steps)) {
+                const int tiles = (n + T - 1) / T;
+                int len = n;
+                if (repulsion) event_chunks(n, bs, chunk, len, nchunk);
+                items = tiles * nchunk;
+                dq.tiles_left[e * kEventLine] = tiles;
+                for (int j = 0; j < tiles; ++j) dq.chunks_left[dq.tile_base[e] + j] = nchunk;
+            } else {
+                atomicAdd(&n_done, 1u);
+            }
+        }
+        int v = items;  // inclusive scan within the wave
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(v, o);
+            if (lane >= o) v += t;
+        }
+        if (lane == 63) wtot[wave] = v;
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            before += q < wave ? wtot[q] : 0;
+            total += wtot[q];
+        }
+        s_base[tid] = carry + (uint32_t)(before + v - items);
+        s_nitems[tid] = items;
+        s_nchunk[tid] = nchunk;
+        __syncthreads();
+        for (int k = wave; k < 1024 && e0 + k < B; k += 16) {
+            const int ni = s_nitems[k], nc = s_nchunk[k];
+            const uint32_t b0 = s_base[k];
+            if ((uint64_t)b0 + (uint64_t)ni > (uint64_t)dq.cap) {
+                if (lane == 0) overflow = 1;
+                continue;
+            }
+            for (int i = lane; i < ni; i += 64) {
+                dq.q[b0 + i] = QItem{e0 + k, i / nc, i % nc, 0};
+                dq.seq[b0 + i] = dq.gen;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) carry += (uint32_t)total;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        Sched *sc = dq.sc;
+        sc->head.v = 0;
+        sc->tail.v = carry;
+        sc->done.v = overflow ? (uint32_t)B : n_done;
+        sc->error.v = overflow ? 2u : 0u;
+        sc->exhausted.v = 0;
+    }
+}
+
+// Drifting holes and the most steps any event took in this call.
+__global__ __launch_bounds__(1024) void k_summary(DevBatch bt, Sched *sc)
+{
+    __shared__ int64_t ssum[16], smax[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int64_t sum = 0, mx = 0;
+    for (int e = tid; e < bt.n_events; e += 1024) {
+        sum += bt.n_act[e];
+        mx = max(mx, bt.call_steps[e]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        sum += __shfl_down(sum, o);
+        mx = max(mx, (int64_t)__shfl_down(mx, o));
+    }
+    if (lane == 0) {
+        ssum[wave] = sum;
+        smax[wave] = mx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int64_t S = 0, M = 0;
+        for (int q = 0; q < 16; ++q) {
+            S += ssum[q];
+            M = max(M, smax[q]);
+        }
+        sc->active = S;
+        sc->max_steps = M;
+    }
+}
+
+// Compaction of every event at seeding (holes already at z <= 0 are out),
+// which also sets the FP32 reference points.  One workgroup per event.
+__global__ __launch_bounds__(256) void k_compact(DevBatch bt)
+{
+    __shared__ int wcount[4];
+    __shared__ double wsum[12];
+    compact_event<256>(bt, blockIdx.x, 0, wcount, wsum);
 }
 
 // Initial clouds (Algorithm 1, initialisation; Eq. 2 width).  One thread per
@@ -655,15 +852,13 @@ __global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int64_t n, int32_t
 }
 
 template <int KT, int BS>
-hipError_t launch_step_t(const DevParams &dp, const DevBatch &bt, const LaunchCfg &cfg, int fp32,
-                         int grid, int field_only, double *field_out, hipStream_t s)
+hipError_t launch_run_t(const DevParams &dp, const DevBatch &bt, const DevQueue &dq,
+                        const RunArgs &ra, int fp32, int grid, hipStream_t s)
 {
     if (fp32)
-        hipLaunchKernelGGL((k_step_f32<KT, BS>), dim3(grid), dim3(BS), 0, s, dp, bt, cfg.chunk,
-                           field_only, field_out);
+        hipLaunchKernelGGL((k_run_f32<KT, BS>), dim3(grid), dim3(BS), 0, s, dp, bt, dq, ra);
     else
-        hipLaunchKernelGGL((k_step_f64<KT, BS>), dim3(grid), dim3(BS), 0, s, dp, bt, cfg.chunk,
-                           field_only, field_out);
+        hipLaunchKernelGGL((k_run_f64<KT, BS>), dim3(grid), dim3(BS), 0, s, dp, bt, dq, ra);
     return hipGetLastError();
 }
 
@@ -672,10 +867,24 @@ int occupancy_t(int fp32)
 {
     int nb = 0;
     hipError_t e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &nb, reinterpret_cast<const void *>(&k_step_f32<KT, BS>), BS, 0)
+                              &nb, reinterpret_cast<const void *>(&k_run_f32<KT, BS>), BS, 0)
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &nb, reinterpret_cast<const void *>(&k_step_f64<KT, BS>), BS, 0);
+                              &nb, reinterpret_cast<const void *>(&k_run_f64<KT, BS>), BS, 0);
     return e == hipSuccess ? nb : -1;
+}
+
+uint64_t idle_ticks()
+{
+    static uint64_t ticks = 0;
+    if (!ticks) {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+            khz <= 0)
+            khz = 100000;  // 100 MHz
+        ticks = (uint64_t)(kIdleSeconds * 1e3 * khz);
+    }
+    return ticks;
 }
 
 }  // namespace
@@ -689,39 +898,48 @@ hipError_t launch_seed(const DevParams &dp, const DevBatch &bt, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const DevParams &dp, const DevBatch &bt, int count_step, hipStream_t s)
+hipError_t launch_compact(const DevParams &dp, const DevBatch &bt, hipStream_t s)
 {
+    (void)dp;
     if (bt.n_events <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_compact, dim3(bt.n_events), dim3(kCompactThreads), 0, s, dp, bt,
-                       count_step);
+    hipLaunchKernelGGL(k_compact, dim3(bt.n_events), dim3(256), 0, s, bt);
     return hipGetLastError();
 }
 
-hipError_t launch_plan(const DevBatch &bt, const LaunchCfg &cfg, hipStream_t s)
+hipError_t launch_init(const DevBatch &bt, const DevQueue &dq, const LaunchCfg &cfg,
+                       int64_t max_steps, int field_only, int repulsion, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, bt, cfg.bs * cfg.kt, cfg.chunk);
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(1024), 0, s, bt, dq, cfg.bs * cfg.kt, cfg.bs,
+                       cfg.chunk, max_steps, field_only, repulsion);
     return hipGetLastError();
 }
 
 #define CT_LAUNCH_CASES(X) \
     X(1, 64) X(2, 64) X(4, 64) X(1, 128) X(2, 128) X(4, 128) X(1, 256) X(2, 256) X(4, 256)
 
-// Persistent step launch over the work list built by launch_plan; field_out
-// receives the field ([N][3], carrier order) when field_only is set.
-hipError_t launch_step(const DevParams &dp, const DevBatch &bt, const LaunchCfg &cfg, int fp32,
-                       int grid, int field_only, double *field_out, hipStream_t s)
+// The persistent run over the queue k_init filled; field_out receives the
+// field ([N][3], carrier order) when field_only is set.
+hipError_t launch_run(const DevParams &dp, const DevBatch &bt, const DevQueue &dq,
+                      const LaunchCfg &cfg, int fp32, int grid, int64_t max_steps, int field_only,
+                      double *field_out, hipStream_t s)
 {
     if (bt.n_events <= 0 || grid <= 0) return hipSuccess;
-#define CT_STEP_CASE(KT_, BS_) \
-    if (cfg.kt == KT_ && cfg.bs == BS_) \
-        return launch_step_t<KT_, BS_>(dp, bt, cfg, fp32, grid, field_only, field_out, s);
-    CT_LAUNCH_CASES(CT_STEP_CASE)
-#undef CT_STEP_CASE
+    RunArgs ra{cfg.chunk, field_only, max_steps, idle_ticks(), field_out};
+#define CT_RUN_CASE(KT_, BS_) \
+    if (cfg.kt == KT_ && cfg.bs == BS_) return launch_run_t<KT_, BS_>(dp, bt, dq, ra, fp32, grid, s);
+    CT_LAUNCH_CASES(CT_RUN_CASE)
+#undef CT_RUN_CASE
     return hipErrorInvalidValue;
 }
 
-// Resident workgroups per compute unit of the step kernel for a configuration.
-int step_occupancy(const LaunchCfg &cfg, int fp32)
+hipError_t launch_summary(const DevBatch &bt, Sched *sc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_summary, dim3(1), dim3(1024), 0, s, bt, sc);
+    return hipGetLastError();
+}
+
+// Resident workgroups per compute unit of the run kernel for a configuration.
+int run_occupancy(const LaunchCfg &cfg, int fp32)
 {
 #define CT_OCC_CASE(KT_, BS_) \
     if (cfg.kt == KT_ && cfg.bs == BS_) return occupancy_t<KT_, BS_>(fp32);
@@ -733,15 +951,6 @@ int step_occupancy(const LaunchCfg &cfg, int fp32)
 bool launch_supported(int kt, int bs)
 {
     return (kt == 1 || kt == 2 || kt == 4) && (bs == 64 || bs == 128 || bs == 256);
-}
-
-hipError_t launch_update(const DevParams &dp, const DevBatch &bt, const LaunchCfg &cfg, int n_max,
-                         int field_only, double *field_out, hipStream_t s)
-{
-    if (bt.n_events <= 0 || n_max <= 0 || cfg.chunk <= 0 || n_max <= cfg.chunk) return hipSuccess;
-    const dim3 grid((n_max + 255) / 256, bt.n_events);
-    hipLaunchKernelGGL(k_update, grid, dim3(256), 0, s, dp, bt, cfg.chunk, field_only, field_out);
-    return hipGetLastError();
 }
 
 hipError_t launch_scatter_alive(const DevBatch &bt, int n_max, hipStream_t s)

@@ -91,6 +91,12 @@ def test_parameter_validation(ct):
     with pytest.raises(ct.CtError) as e:
         ct.ct_init_sensor(p)
     assert e.value.status == -1
+    for bits in (2, 8, 1 << 20):  # only CT_OPT_TIMING and CT_OPT_AUTOTUNE exist
+        p = ct.make_params(Sensor())
+        p.options = bits
+        with pytest.raises(ct.CtError) as e:
+            ct.ct_init_sensor(p)
+        assert e.value.status == -1, bits
 
 
 def test_carrier_counts_follow_algorithm1(ct):

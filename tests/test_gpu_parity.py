@@ -139,7 +139,7 @@ def test_field_matches_oracle(ct, n, prec):
     K = oracle.coulomb_k(s)
     ref = oracle.field(s, xyz)
     bound = field_error_bound(xyz, s.softening_um, K, prec == FP32)
-    for launch in [None, (1, 128, 0), (4, 256, 0), (2, 128, 256)]:
+    for launch in [None, (1, 128, 128), (4, 256, 256), (2, 128, 512), (1, 64, 64)]:
         with ct.Simulator(s, prec, launch=launch) as sim:
             sim.seed(explicit_batch([xyz]))
             E = sim.field()
@@ -214,8 +214,8 @@ def test_batch_8kev_sampled_events(ct, batch256):
           f"fp32 vs fp64 all 256 events {df:.2e}")
 
 
-@pytest.mark.parametrize("launch", [None, (1, 128, 0), (2, 256, 0), (4, 256, 0), (4, 128, 0),
-                                    (2, 256, 256), (1, 128, 384)])
+@pytest.mark.parametrize("launch", [None, (1, 128, 128), (2, 256, 256), (4, 256, 1024),
+                                    (4, 128, 256), (2, 256, 512), (1, 64, 64), (1, 256, 768)])
 def test_ragged_batch_all_launches(ct, launch):
     rng = np.random.default_rng(21)
     sizes = [0, 1, 2, 63, 64, 65, 300, 1025]
@@ -397,23 +397,43 @@ def test_error_paths(ct):
         sim.seed(explicit_batch([np.zeros((0, 3)), [[0, 0, -1.0]]]))
         r = sim.collect()
         assert r["pix"][1].sum() == 1 and r["pix"][0].sum() == 0
+        for bad in ((1, 256, 300), (1, 128, 64), (3, 256, 768), (1, 256, (1 << 20) + 256)):
+            with pytest.raises(ct.CtError) as e:
+                sim.set_launch(*bad)
+            assert e.value.status == -1  # CT_EINVAL
 
 
-def test_graph_equals_eager_bitwise(ct):
-    """The captured step loop, eager launches and the timed variant give the
-    same bits; the timed variant reports the step-kernel time."""
+def test_runs_bitwise_reproducible_and_timed(ct):
+    """Repeated runs, and the timed variant, give the same bits (the order in
+    which work items complete does not enter the result); the timed variant
+    reports the step-kernel time of its one run."""
     s, b = batch_8kev(n_events=8, seed=6)
     for prec in (FP64, FP32):
         g = gpu_run(ct, s, b, prec)
-        with ct.Simulator(s, prec, options=ct.CT_OPT_NO_GRAPH) as sim:
-            e = sim.run(b)
+        again = gpu_run(ct, s, b, prec)
         with ct.Simulator(s, prec, options=ct.CT_OPT_TIMING) as sim:
             t = sim.run(b)
-        for r in (e, t):
+        for r in (again, t):
             np.testing.assert_array_equal(g["xyz"], r["xyz"])
             np.testing.assert_array_equal(g["cstep"], r["cstep"])
             np.testing.assert_array_equal(g["pix"], r["pix"])
-        assert t["stats"].field_launches >= t["steps"].max() and t["stats"].field_kernel_ms > 0
+        assert t["stats"].field_launches == 1 and t["stats"].field_kernel_ms > 0
+        assert g["stats"].workgroups > 0 and g["stats"].chunk_len == 768
+
+
+def test_full_work_queue_parks_and_resumes(ct, monkeypatch):
+    """A work queue that holds only the first step's items parks events as
+    soon as it is full (one or a few steps per run); the host runs again until
+    all are done, and the result is bitwise the default one."""
+    s, b = batch_8kev(n_events=6, seed=12)
+    ref = gpu_run(ct, s, b, FP32, launch=(1, 256, 512))
+    monkeypatch.setenv("CT_QUEUE_STEPS", "1")
+    with ct.Simulator(s, FP32, options=ct.CT_OPT_TIMING, launch=(1, 256, 512)) as sim:
+        r = sim.run(b)
+    assert r["stats"].field_launches > r["steps"].max() // 4 > 1
+    np.testing.assert_array_equal(ref["xyz"], r["xyz"])
+    np.testing.assert_array_equal(ref["cstep"], r["cstep"])
+    np.testing.assert_array_equal(ref["pix"], r["pix"])
 
 
 def test_autotuned_launch_matches_oracle(ct):
@@ -425,6 +445,7 @@ def test_autotuned_launch_matches_oracle(ct):
             g = sim.run(b)
         st = g["stats"]
         assert st.block_size in (128, 256) and st.targets_per_thread in (1, 2)
+        assert st.chunk_len in (512, 768, 1024)
         for e in (0, 31, 63):
             o = oracle.run(s, b.event(e))
             if prec == FP64:
