@@ -135,7 +135,7 @@ double initial_sigma(const ct_event_desc &e)
 
 // Byte layout of one batch inside a single device buffer.
 struct Layout {
-    size_t off, n_act, ev_step, ev_taken, call_steps, ref, pos, idx, rngid, out_xyz, out_cstep, pix,
+    size_t off, n_act, ev_step, ev_taken, call_steps, ref, pos, idx, nidx, rngid, out_xyz, out_cstep, pix,
         pairs, hsteps, sigma, dep_off, deposits, x_off, xyz_in, start, total;
 };
 
@@ -158,6 +158,7 @@ Layout make_layout(int64_t B, int64_t N, int64_t n_dep, int64_t n_exp, int G1)
     L.ref = take(sizeof(double) * 4 * B);
     L.pos = take(sizeof(double) * 6 * N);
     L.idx = take(sizeof(int32_t) * N);
+    L.nidx = take(sizeof(int32_t) * N);
     L.rngid = take(sizeof(int32_t) * N);
     L.out_xyz = take(sizeof(double) * 3 * N);
     L.out_cstep = take(sizeof(int32_t) * N);
@@ -450,10 +451,13 @@ ct_status run_once(ct_ctx *c, const ct::LaunchCfg &cfg, int64_t max_steps, int f
     }
     if (c->h_sched->error.v) {
         c->broken = true;
-        return fail(CT_EDEVICE, "%s", c->h_sched->error.v == 2u
-                                          ? "work queue too small for the first step (internal error)"
-                                          : "step kernel stopped: no event step queued or finished "
-                                            "for 10 s");
+        const uint32_t *w = c->h_sched->stall.pad;
+        if (c->h_sched->error.v == 2u)
+            return fail(CT_EDEVICE, "work queue too small for the first step (internal error)");
+        return fail(CT_EDEVICE,
+                    "step kernel stopped: no event step queued or finished for 10 s (waiting for "
+                    "ticket %u; head %u, tail %u, events done %u of %d)",
+                    w[0], w[1], w[2], w[3], (int)c->shape.B);
     }
     return CT_OK;
 }
@@ -723,6 +727,7 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     bt.ny = pos + 4 * s.N;
     bt.nz = pos + 5 * s.N;
     bt.idx = at<int32_t>(w, L.idx);
+    bt.nidx = at<int32_t>(w, L.nidx);
     bt.rngid = at<int32_t>(w, L.rngid);
     bt.out_xyz = at<double>(w, L.out_xyz);
     bt.out_cstep = at<int32_t>(w, L.out_cstep);

@@ -28,9 +28,11 @@ struct DevParams {
 constexpr int kMaxChunks = 256;
 
 // One work item: target tile `tile` of event `e` (bs * kt targets) against
-// source chunk `chunk` of the same event, for the event's current step.
+// source chunk `chunk` of the same event, for the event's current step, in
+// which the event has `n` drifting holes (the item's split into tiles and
+// chunks follows from n alone).
 struct QItem {
-    int32_t e, tile, chunk, pad;
+    int32_t e, tile, chunk, n;
 };
 
 // Control block of one run of the persistent step kernel.  Tickets index the
@@ -48,6 +50,7 @@ struct Sched {
     Line done;       // events finished for this run (drained, at the step cap, or parked)
     Line error;      // 1: the liveness guard expired; 2: the first step did not fit the queue
     Line exhausted;  // 1: some event was parked because the queue was full
+    Line stall;      // when the guard expires: ticket waited for, head, tail, done
     int64_t active;      // drifting holes (summary kernel)
     int64_t max_steps;   // most steps any event took in this call (summary kernel)
 };
@@ -71,6 +74,7 @@ struct DevBatch {
     double *cx, *cy, *cz;   // [N] current positions (compacted)
     double *nx, *ny, *nz;   // [N] positions after the step (same slots)
     int32_t *idx;           // [N] carrier index within its event, per slot (compacted)
+    int32_t *nidx;          // [N] the same after the step (same slots as nx)
     const int32_t *rngid;   // [N] RNG carrier id by carrier (event offset + index)
     double *out_xyz;        // [N][3] by carrier
     int32_t *out_cstep;     // [N] by carrier

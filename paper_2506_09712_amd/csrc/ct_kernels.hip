@@ -80,14 +80,19 @@ __device__ void normals3(const DevParams &dp, Ctr ctr, double n[3])
 // Publication between workgroups of one run.  Data that other workgroups
 // read later in the same run is stored with agent-scope relaxed atomic
 // stores, which go to device-coherent memory instead of staying dirty in the
-// L2 of this XCD.  After a workgroup barrier (all waves of a workgroup share
-// one CU and its in-order vector memory path), thread 0 publishes with a
-// release operation on a completion counter or flag; its L2 write-back then
-// has almost nothing to do.  The observing thread reads the flag, executes an
-// acquire fence (invalidating stale cache lines), and a workgroup barrier
-// orders the rest of its workgroup's loads after it.
+// L2 of this XCD.  Every thread then waits for its own stores to complete
+// (vmcnt 0, no cache maintenance), the workgroup meets at a barrier, and
+// thread 0 alone publishes with a release operation on a completion counter
+// or flag: one L2 write-back per workgroup, with almost nothing left to write
+// back.  (A release fence in every thread costs one write-back per wave,
+// several times more under load.)  The observing thread reads the flag,
+// executes an acquire fence (invalidating stale cache lines), and a
+// workgroup barrier orders the rest of its workgroup's loads after it.
 __device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// s_waitcnt vmcnt(0): this thread's vector memory operations have completed.
+__device__ __forceinline__ void wait_own_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 __device__ __forceinline__ void st_dev(double *p, double v)
 {
@@ -183,6 +188,7 @@ __device__ void advance(const DevParams &dp, const DevBatch &bt, int b, int slot
     st_dev(&bt.nx[slot], x1);
     st_dev(&bt.ny[slot], y1);
     st_dev(&bt.nz[slot], z1);
+    st_dev(&bt.nidx[slot], k);
     if (z1 <= 0.0) collect(dp, bt, b, carrier, x1, y1, z1, step + 1);
 }
 
@@ -274,60 +280,74 @@ __device__ __forceinline__ void pair_f64(const D4 &s, double s2, const double (&
 
 // Holes of event b with z > 0 after the step survive; they are packed to the
 // front of the event's slots in carrier order by the NT threads of one
-// workgroup.  Each wave ranks its survivors with a 64-bit ballot and mbcnt,
-// the workgroup adds the wave totals; carrier indices are compacted in place
-// (every read of a chunk precedes the barrier, every write follows it and
-// lands at or below it).  Thread 0 stores the new count and centroid (summed
-// in a fixed order) and, for a step, counts it.  Returns the survivors (in
-// every thread); ends with a barrier.
+// workgroup, from the post-step arrays (nx, ny, nz, nidx) into the current
+// ones (cx, cy, cz, idx).  Windows of kCompactChunks chunks of NT slots:
+// every z of a window is loaded at once, each wave ranks its survivors with
+// a 64-bit ballot and mbcnt per chunk, one barrier publishes the wave totals,
+// and the survivors are copied with independent loads and stores, so about
+// two memory latencies are exposed per window.  n is the event's count
+// before the step.  Thread 0 stores the new count and centroid (summed in a
+// fixed order) and, for a step, counts it.  Returns the survivors (in every
+// thread); ends with a barrier.
+constexpr int kCompactChunks = 8;
+
 template <int NT>
-__device__ int compact_event(const DevBatch &bt, int b, int count_step, int *wcount, double *wsum)
+__device__ int compact_event(const DevBatch &bt, int b, int n, int count_step, int *wcount,
+                             double *wsum)
 {
     constexpr int W = NT / 64;
-    const int n = bt.n_act[b];
+    constexpr int K = kCompactChunks;
     const int base = bt.off[b];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     int kept = 0;
     double sx = 0.0, sy = 0.0, sz = 0.0;
-    for (int c0 = 0; c0 < n; c0 += NT) {
-        const int i = c0 + tid;
-        bool alive = false;
-        double x = 0.0, y = 0.0, z = 0.0;
-        int k = 0;
-        if (i < n) {
-            z = bt.nz[base + i];
-            alive = z > 0.0;
-            if (alive) {
-                x = bt.nx[base + i];
-                y = bt.ny[base + i];
-                k = bt.idx[base + i];
-            }
-        }
-        const uint64_t mask = __ballot(alive);
-        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-        if (lane == 0) wcount[wave] = __popcll(mask);
-        __syncthreads();
-        int before = 0, total = 0;
+    for (int w0 = 0; w0 < n; w0 += K * NT) {
+        double z[K];
 #pragma unroll
-        for (int q = 0; q < W; ++q) {
-            const int v = wcount[q];
-            before += q < wave ? v : 0;
-            total += v;
+        for (int j = 0; j < K; ++j) {
+            const int i = w0 + j * NT + tid;
+            z[j] = i < n ? bt.nz[base + i] : 0.0;
         }
-        if (alive) {
-            const int d = base + kept + before + rank;
-            st_dev(&bt.cx[d], x);
-            st_dev(&bt.cy[d], y);
-            st_dev(&bt.cz[d], z);
-            st_dev(&bt.idx[d], k);
-            sx += x;
-            sy += y;
-            sz += z;
+        uint32_t alive = 0;  // bit j: this thread's slot of chunk j survives
+        int rank[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const bool a = z[j] > 0.0;
+            const uint64_t mask = __ballot(a);
+            rank[j] = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            if (lane == 0) wcount[j * W + wave] = __popcll(mask);
+            alive |= (a ? 1u : 0u) << j;
         }
-        kept += total;
         __syncthreads();
+        int before = kept;  // survivors ahead of this thread's slot in the current chunk
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            int mine = 0, total = 0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const int v = wcount[j * W + q];
+                mine += q < wave ? v : 0;
+                total += v;
+            }
+            if (alive & (1u << j)) {
+                const int i = w0 + j * NT + tid;
+                const int d = base + before + mine + rank[j];
+                const double x = bt.nx[base + i], y = bt.ny[base + i];
+                const int k = bt.nidx[base + i];
+                st_dev(&bt.cx[d], x);
+                st_dev(&bt.cy[d], y);
+                st_dev(&bt.cz[d], z[j]);
+                st_dev(&bt.idx[d], k);
+                sx += x;
+                sy += y;
+                sz += z[j];
+            }
+            before += total;
+        }
+        kept = before;
+        __syncthreads();  // wave totals of this window are read before the next overwrites them
     }
     for (int o = 32; o > 0; o >>= 1) {
         sx += __shfl_down(sx, o);
@@ -421,7 +441,12 @@ __device__ int claim(const DevQueue &dq, uint32_t n_events, uint64_t idle_ticks,
                 seen_done = dn;
                 since = now;
             } else if (now - since > idle_ticks) {
-                st_relaxed(&sc->error.v, 1u);
+                if (atomicCAS(&sc->error.v, 0u, 1u) == 0u) {  // first to give up: record why
+                    st_relaxed(&sc->stall.pad[0], t);
+                    st_relaxed(&sc->stall.pad[1], ld_relaxed(&sc->head.v));
+                    st_relaxed(&sc->stall.pad[2], tl);
+                    st_relaxed(&sc->stall.pad[3], dn);
+                }
                 return 0;
             }
         }
@@ -430,7 +455,11 @@ __device__ int claim(const DevQueue &dq, uint32_t n_events, uint64_t idle_ticks,
         else __builtin_amdgcn_s_sleep(127);
     }
     fence_acquire();
-    out = dq.q[t];
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(dq.q + t);
+    out.e = (int32_t)ld_relaxed(w);
+    out.tile = (int32_t)ld_relaxed(w + 1);
+    out.chunk = (int32_t)ld_relaxed(w + 2);
+    out.n = (int32_t)ld_relaxed(w + 3);
     return 1;
 }
 
@@ -442,7 +471,7 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
     constexpr int W = BS / 64;
     __shared__ QItem s_item;
     __shared__ int s_go;
-    __shared__ int s_wcount[W];
+    __shared__ int s_wcount[kCompactChunks * W];
     __shared__ double s_wsum[3 * W];
     __shared__ int s_items, s_tiles, s_chunks;
     __shared__ uint32_t s_t0;
@@ -462,7 +491,7 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
         if (!s_go) break;
         const QItem it = s_item;
         const int b = it.e;
-        const int n = bt.n_act[b];
+        const int n = it.n;
         const int base = bt.off[b];
         const int n0 = bt.off[b + 1] - base;
         int len = n, chunks = 1;
@@ -559,6 +588,7 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
                     st_dev(&dq.part[po + 2 * n0 + s], ez[m]);
                 }
             }
+            wait_own_stores();
             __syncthreads();
             if (tid == 0) s_go = dec_is_last(&dq.chunks_left[dq.tile_base[b] + it.tile]);
             __syncthreads();
@@ -583,6 +613,7 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
                 field_or_advance(dp, bt, b, base + s, dp.K * ex[m], dp.K * ey[m], dp.K * ez[m],
                                  ra.field_only, ra.field_out);
         }
+        wait_own_stores();
         __syncthreads();
         if (tid == 0) s_go = dec_is_last(&dq.tiles_left[b * kEventLine]);
         __syncthreads();
@@ -593,7 +624,7 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
             if (tid == 0) add_relaxed(&sc->done.v, 1u);
             continue;
         }
-        const int kept = compact_event<BS>(bt, b, 1, s_wcount, s_wsum);
+        const int kept = compact_event<BS>(bt, b, n, 1, s_wcount, s_wsum);
         if (tid == 0) {
             int items = 0, tiles = 0, nchunk = 1;
             uint32_t t0q = 0;
@@ -627,9 +658,12 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
                 st_dev(w, b);
                 st_dev(w + 1, i / nchunk);
                 st_dev(w + 2, i % nchunk);
+                st_dev(w + 3, kept);
             }
+            wait_own_stores();
             __syncthreads();
-            fence_release();
+            if (tid == 0) fence_release();
+            __syncthreads();  // the write-back has completed before any sequence word is set
             for (int i = tid; i < items; i += BS) st_relaxed(&dq.seq[t0q + i], dq.gen);
         }
     }
@@ -713,7 +747,7 @@ __global__ __launch_bounds__(1024) void k_init(DevBatch bt, DevQueue dq, int T, 
                 continue;
             }
             for (int i = lane; i < ni; i += 64) {
-                dq.q[b0 + i] = QItem{e0 + k, i / nc, i % nc, 0};
+                dq.q[b0 + i] = QItem{e0 + k, i / nc, i % nc, bt.n_act[e0 + k]};
                 dq.seq[b0 + i] = dq.gen;
             }
         }
@@ -727,6 +761,7 @@ __global__ __launch_bounds__(1024) void k_init(DevBatch bt, DevQueue dq, int T, 
         sc->tail.v = carry;
         sc->done.v = overflow ? (uint32_t)B : n_done;
         sc->error.v = overflow ? 2u : 0u;
+        sc->stall.pad[0] = sc->stall.pad[1] = sc->stall.pad[2] = sc->stall.pad[3] = 0;
         sc->exhausted.v = 0;
     }
 }
@@ -765,9 +800,9 @@ __global__ __launch_bounds__(1024) void k_summary(DevBatch bt, Sched *sc)
 // which also sets the FP32 reference points.  One workgroup per event.
 __global__ __launch_bounds__(256) void k_compact(DevBatch bt)
 {
-    __shared__ int wcount[4];
+    __shared__ int wcount[kCompactChunks * 4];
     __shared__ double wsum[12];
-    compact_event<256>(bt, blockIdx.x, 0, wcount, wsum);
+    compact_event<256>(bt, blockIdx.x, bt.n_act[blockIdx.x], 0, wcount, wsum);
 }
 
 // Initial clouds (Algorithm 1, initialisation; Eq. 2 width).  One thread per
@@ -802,7 +837,7 @@ __global__ __launch_bounds__(256) void k_seed(DevParams dp, DevBatch bt)
         z = p[2];
     }
     if (z > dp.H) z = 2.0 * dp.H - z;
-    bt.idx[g] = k;
+    bt.nidx[g] = k;
     bt.nx[g] = x;
     bt.ny[g] = y;
     bt.nz[g] = z;
