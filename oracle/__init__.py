@@ -20,7 +20,7 @@ _SRC = os.path.join(_HERE, "ct_oracle.c")
 _LIB = os.path.join(_HERE, "libct_oracle.so")
 
 OK, EINVAL, EMAXSTEPS, ENONFINITE = 0, -1, -5, -6
-REPULSION, DRIFT, DIFFUSION = 1, 2, 4
+REPULSION, DRIFT, DIFFUSION, ELECTRONS = 1, 2, 4, 8
 
 
 def build(force: bool = True) -> str:
@@ -42,6 +42,8 @@ class OcParams(C.Structure):
         ("pair_energy_ev", C.c_double), ("mobility", C.c_int32),
         ("mu0_override", C.c_double), ("ec_override", C.c_double), ("beta_override", C.c_double),
         ("physics", C.c_uint32), ("seed", C.c_uint64), ("max_steps", C.c_int64),
+        ("mu0_e_override", C.c_double), ("ec_e_override", C.c_double),
+        ("beta_e_override", C.c_double),
     ]
 
 
@@ -50,6 +52,7 @@ class OcEvent(C.Structure):
         ("energy_kev", C.c_double), ("n_carriers", C.c_int32), ("n_deposits", C.c_int32),
         ("sigma_um", C.c_double), ("deposits", C.POINTER(C.c_double)),
         ("xyz", C.POINTER(C.c_double)), ("ids", C.POINTER(C.c_int32)), ("start_step", C.c_int64),
+        ("n_electrons", C.c_int32),
     ]
 
 
@@ -70,6 +73,12 @@ def lib():
         L.oc_thermal_voltage.argtypes = [C.POINTER(OcParams)]
         L.oc_thermal_voltage.restype = C.c_double
         L.oc_mobility_params.argtypes = [C.POINTER(OcParams), dp]
+        L.oc_mobility_params_of.argtypes = [C.POINTER(OcParams), C.c_int, dp]
+        L.oc_mobility_of.argtypes = [C.POINTER(OcParams), C.c_int, C.c_double]
+        L.oc_mobility_of.restype = C.c_double
+        L.oc_field_q.argtypes = [C.POINTER(OcParams), C.c_int64, dp, dp, dp]
+        L.oc_electron_count.argtypes = [C.POINTER(OcParams), C.POINTER(OcEvent)]
+        L.oc_electron_count.restype = C.c_int32
         L.oc_mobility.argtypes = [C.POINTER(OcParams), C.c_double]
         L.oc_mobility.restype = C.c_double
         L.oc_drift_field.argtypes = [C.POINTER(OcParams), C.c_double]
@@ -99,12 +108,13 @@ def _dp(a: Optional[np.ndarray]):
 
 def params(sensor) -> OcParams:
     flags = (REPULSION if sensor.repulsion else 0) | (DRIFT if sensor.drift else 0) | \
-            (DIFFUSION if sensor.diffusion else 0)
+            (DIFFUSION if sensor.diffusion else 0) | (ELECTRONS if sensor.electrons else 0)
     mob = {"jacoboni": 0, "constant": 1}[sensor.mobility]
     return OcParams(sensor.thickness_um, sensor.v_bias, sensor.v_dep, sensor.temperature_k,
                     sensor.pitch_um, sensor.grid_n, sensor.dt_ns, sensor.softening_um, sensor.eps_r,
                     sensor.pair_energy_ev, mob, sensor.mu0_override, sensor.ec_override,
-                    sensor.beta_override, flags, sensor.seed, sensor.max_steps)
+                    sensor.beta_override, flags, sensor.seed, sensor.max_steps,
+                    sensor.mu0_e_override, sensor.ec_e_override, sensor.beta_e_override)
 
 
 def set_threads(n: int) -> None:
@@ -137,14 +147,15 @@ def thermal_voltage(sensor) -> float:
     return float(lib().oc_thermal_voltage(C.byref(params(sensor))))
 
 
-def mobility_params(sensor) -> tuple:
+def mobility_params(sensor, electron: bool = False) -> tuple:
+    """(mu0 [um^2/(V ns)], Ec [V/um], beta) of holes or electrons."""
     o = (C.c_double * 3)()
-    lib().oc_mobility_params(C.byref(params(sensor)), o)
+    lib().oc_mobility_params_of(C.byref(params(sensor)), int(electron), o)
     return tuple(o)
 
 
-def mobility(sensor, e_mag: float) -> float:
-    return float(lib().oc_mobility(C.byref(params(sensor)), float(e_mag)))
+def mobility(sensor, e_mag: float, electron: bool = False) -> float:
+    return float(lib().oc_mobility_of(C.byref(params(sensor)), int(electron), float(e_mag)))
 
 
 def drift_field(sensor, z: float) -> float:
@@ -160,6 +171,15 @@ def field(sensor, xyz: np.ndarray) -> np.ndarray:
     xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
     E = np.zeros_like(xyz)
     lib().oc_field(C.byref(params(sensor)), xyz.shape[0], _dp(xyz), _dp(E))
+    return E
+
+
+def field_q(sensor, xyz: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """Field (V/um) of carriers with charges q (+1 hole, -1 electron) on each other."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+    E = np.zeros_like(xyz)
+    lib().oc_field_q(C.byref(params(sensor)), xyz.shape[0], _dp(xyz), _dp(q), _dp(E))
     return E
 
 
@@ -184,21 +204,33 @@ def _events(batch):
         dep = np.ascontiguousarray(batch.deposits[doff[b]:doff[b + 1]]) if nd > 0 else None
         xyz = None
         if nd == 0:
-            n = int(batch.n_carriers[b])
+            n = int(batch.n_carriers[b]) + max(int(batch.n_electrons[b]), 0)
             xyz = np.ascontiguousarray(batch.xyz[xo:xo + n])
             xo += n
         keep += [dep, xyz]
         evs[b] = OcEvent(float(batch.energy_kev[b]), int(batch.n_carriers[b]), nd,
                          float(batch.sigma_um[b]), _dp(dep), _dp(xyz), None,
-                         int(batch.start_step[b]))
+                         int(batch.start_step[b]), int(batch.n_electrons[b]))
     return evs, keep
 
 
-def carrier_counts(sensor, batch) -> np.ndarray:
+def hole_counts(sensor, batch) -> np.ndarray:
     evs, keep = _events(batch)
     p = params(sensor)
     return np.array([lib().oc_carrier_count(C.byref(p), C.byref(evs[b]))
                      for b in range(batch.n_events)], dtype=np.int64)
+
+
+def electron_counts(sensor, batch) -> np.ndarray:
+    evs, keep = _events(batch)
+    p = params(sensor)
+    return np.array([lib().oc_electron_count(C.byref(p), C.byref(evs[b]))
+                     for b in range(batch.n_events)], dtype=np.int64)
+
+
+def carrier_counts(sensor, batch) -> np.ndarray:
+    """Carriers of each event: its holes and (with the electron species) electrons."""
+    return np.maximum(hole_counts(sensor, batch), 0) + np.maximum(electron_counts(sensor, batch), 0)
 
 
 def initial_sigma(batch, b: int = 0) -> float:
@@ -226,4 +258,5 @@ def run(sensor, batch, threads: Optional[int] = None) -> dict:
                       cstep.ctypes.data_as(C.POINTER(C.c_int32)),
                       steps.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(pairs), C.byref(hsteps))
     return {"status": int(st), "pix": pix, "xyz": xyz, "cstep": cstep, "steps": steps,
-            "pairs": int(pairs.value), "hole_steps": int(hsteps.value), "offsets": off, "n": n}
+            "pairs": int(pairs.value), "hole_steps": int(hsteps.value), "offsets": off, "n": n,
+            "n_holes": np.maximum(hole_counts(sensor, batch), 0)}

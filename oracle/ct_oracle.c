@@ -17,16 +17,30 @@
  *    H - z here.  Holes drift towards z = 0 and are collected once an update
  *    leaves them at z <= 0.  An update that crosses the entrance side z = H
  *    is mirrored back (z -> 2H - z).
- *  - Repulsion field (Eq. 4, holes only, q_j = +e):
- *        E_i = K * sum_{j != i, alive} (r_i - r_j) / (|r_i - r_j|^2 + s^2)^(3/2)
- *    with K = e / (4 pi eps0 eps_r) and Plummer softening s (s = 0 is Eq. 4
- *    exactly).  Eq. 4 prints q_i q_j, which is a force; the field acting on
- *    a hole is the sum of q_j r_ij / (4 pi eps0 eps_r r^3).
+ *  - Repulsion field (Eq. 4):
+ *        E_i = K * sum_{j != i, alive} q_j (r_i - r_j) / (|r_i - r_j|^2 + s^2)^(3/2)
+ *    with q_j = +1 for holes and -1 for electrons, K = e / (4 pi eps0 eps_r)
+ *    and Plummer softening s (s = 0 is Eq. 4 exactly).  Eq. 4 prints
+ *    q_i q_j, which is a force: the field at carrier i is the sum of
+ *    q_j r_ij / (4 pi eps0 eps_r r^3), and carrier i moves along q_i times
+ *    it (holes along the field, electrons against it), which makes like
+ *    charges repel and opposite charges attract (Sec. 2.1 and its footnote).
+ *  - Two species (optional, physics bit 3): besides its holes, an event
+ *    simulates electrons (Sec. 2.1, "both electrons and holes are simulated
+ *    as individual charge carriers").  Electron k of a cloud event starts at
+ *    the position of hole k (the pair is created at one point).  Electrons
+ *    drift away from the pixel plane with the Jacoboni-Canali electron laws,
+ *    are collected at the entrance side (an update that leaves them at
+ *    z >= H) and mirrored at the pixel plane (z -> -z); they are not counted
+ *    in pixels.  An event ends when its last hole is collected (Algorithm 1:
+ *    "until all holes reach the readout electrode"); electrons still
+ *    drifting then keep their current position.
  *  - Drift field (Eq. 6, rewritten for this z axis):
  *        E_z(z) = -[(Vb + Vd)/H - 2 Vd z / H^2]
  *  - Mobility: Caughey-Thomas form mu = mu0 / (1 + (E/Ec)^beta)^(1/beta)
  *    evaluated at |E_drift + E_rep| (Sec. 2.1, Algorithm 1), with the
- *    Jacoboni-Canali hole temperature laws for mu0 = vm/Ec, Ec and beta.
+ *    Jacoboni-Canali temperature laws for mu0 = vm/Ec, Ec and beta of each
+ *    species.
  *  - Diffusion: D = mu k T / e (Einstein relation, Eq. 1); each axis moves
  *    by sqrt(2 D dt) times a standard normal draw (Eqs. 3 and 5).
  *  - Update order: every alive carrier is moved from the same snapshot of
@@ -34,8 +48,8 @@
  *    per-carrier update loop).
  *  - Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11),
  *    key = (seed low 32 bits, seed high 32 bits), counter =
- *    (carrier id, step, event id, domain); domain 0 = diffusion at a step,
- *    domain 1 = initial cloud.  Uniforms (w + 0.5) 2^-32, Box-Muller
+ *    (carrier id, step, event id, domain); domain 0 = hole diffusion at a
+ *    step, domain 1 = initial cloud, domain 4 = electron diffusion at a step.  Uniforms (w + 0.5) 2^-32, Box-Muller
  *    normals: n0, n1 from (u0, u1), n2 from (u2, u3).
  *  - Pixel integration: a grid_n x grid_n array of square pixels of side
  *    pitch centred on (0, 0); bin index floor((x + grid_n pitch / 2) / pitch)
@@ -56,11 +70,12 @@ typedef struct {
     double pitch_um;
     int32_t grid_n;
     double dt_ns, softening_um, eps_r, pair_energy_ev;
-    int32_t mobility; /* 0 = Caughey-Thomas with Jacoboni-Canali hole laws, 1 = constant mu0 */
-    double mu0_override, ec_override, beta_override; /* NaN = model value at T */
-    uint32_t physics; /* bit 0 repulsion, bit 1 drift, bit 2 diffusion */
+    int32_t mobility; /* 0 = Caughey-Thomas with Jacoboni-Canali laws, 1 = constant mu0 */
+    double mu0_override, ec_override, beta_override; /* holes; NaN = model value at T */
+    uint32_t physics; /* bit 0 repulsion, bit 1 drift, bit 2 diffusion, bit 3 electrons */
     uint64_t seed;
     int64_t max_steps;
+    double mu0_e_override, ec_e_override, beta_e_override; /* electrons; NaN = model value */
 } oc_params;
 
 typedef struct {
@@ -70,12 +85,15 @@ typedef struct {
     double sigma_um;    /* < 0: Eq. 2 */
     const double *deposits; /* [n_deposits][3] */
     const double *xyz;      /* [n_carriers][3] when n_deposits == 0 */
-    const int32_t *ids;     /* optional carrier ids for the RNG counter (default i) */
+    const int32_t *ids;     /* optional carrier ids for the RNG counter (default: index
+                               within the species) */
     int64_t start_step;
+    int32_t n_electrons;    /* with electrons: < 0 = one per hole; explicit events list the
+                               electrons' positions (and ids) after the holes' */
 } oc_event;
 
 enum { OC_OK = 0, OC_EINVAL = -1, OC_EMAXSTEPS = -5, OC_ENONFINITE = -6 };
-enum { OC_REPULSION = 1u, OC_DRIFT = 2u, OC_DIFFUSION = 4u };
+enum { OC_REPULSION = 1u, OC_DRIFT = 2u, OC_DIFFUSION = 4u, OC_ELECTRONS = 8u };
 
 /* SI exact values (e, k) and CODATA 2022 vacuum permittivity */
 static const double E_CHARGE = 1.602176634e-19; /* C */
@@ -142,30 +160,46 @@ double oc_coulomb_k(const oc_params *p) { return E_CHARGE / (4.0 * PI * EPS0 * p
 double oc_thermal_voltage(const oc_params *p) { return K_BOLTZ * p->temperature_k / E_CHARGE; }
 
 /* Mobility-model parameters at temperature T: mu0 [um^2/(V ns)], Ec [V/um],
- * beta.  Jacoboni-Canali hole laws: vm = 1.62e8 T^-0.52 cm/s,
- * Ec = 1.24 T^1.68 V/cm, beta = 0.46 T^0.17, and mu0 = vm / Ec. */
-void oc_mobility_params(const oc_params *p, double out[3])
+ * beta, for holes (electron = 0) or electrons (electron = 1).
+ * Jacoboni-Canali laws (Solid-State Electron. 20 (1977) 77), with mu0 = vm/Ec:
+ *   holes:     vm = 1.62e8 T^-0.52 cm/s, Ec = 1.24 T^1.68 V/cm, beta = 0.46 T^0.17
+ *   electrons: vm = 1.53e9 T^-0.87 cm/s, Ec = 1.01 T^1.55 V/cm, beta = 2.57e-2 T^0.66 */
+void oc_mobility_params_of(const oc_params *p, int electron, double out[3])
 {
     const double T = p->temperature_k;
-    const double vm = 1.62e8 * pow(T, -0.52) * 1e-5; /* cm/s -> um/ns */
-    double ec = 1.24 * pow(T, 1.68) * 1e-4;          /* V/cm -> V/um */
-    double beta = 0.46 * pow(T, 0.17);
+    double vm, ec, beta;
+    if (electron) {
+        vm = 1.53e9 * pow(T, -0.87) * 1e-5; /* cm/s -> um/ns */
+        ec = 1.01 * pow(T, 1.55) * 1e-4;    /* V/cm -> V/um */
+        beta = 2.57e-2 * pow(T, 0.66);
+    } else {
+        vm = 1.62e8 * pow(T, -0.52) * 1e-5;
+        ec = 1.24 * pow(T, 1.68) * 1e-4;
+        beta = 0.46 * pow(T, 0.17);
+    }
     double mu0 = vm / ec;
-    if (!isnan(p->mu0_override)) mu0 = p->mu0_override;
-    if (!isnan(p->ec_override)) ec = p->ec_override;
-    if (!isnan(p->beta_override)) beta = p->beta_override;
+    const double o_mu0 = electron ? p->mu0_e_override : p->mu0_override;
+    const double o_ec = electron ? p->ec_e_override : p->ec_override;
+    const double o_beta = electron ? p->beta_e_override : p->beta_override;
+    if (!isnan(o_mu0)) mu0 = o_mu0;
+    if (!isnan(o_ec)) ec = o_ec;
+    if (!isnan(o_beta)) beta = o_beta;
     out[0] = mu0;
     out[1] = ec;
     out[2] = beta;
 }
 
-double oc_mobility(const oc_params *p, double e_mag)
+void oc_mobility_params(const oc_params *p, double out[3]) { oc_mobility_params_of(p, 0, out); }
+
+double oc_mobility_of(const oc_params *p, int electron, double e_mag)
 {
     double m[3];
-    oc_mobility_params(p, m);
+    oc_mobility_params_of(p, electron, m);
     if (p->mobility == 1) return m[0];
     return m[0] / pow(1.0 + pow(e_mag / m[1], m[2]), 1.0 / m[2]);
 }
+
+double oc_mobility(const oc_params *p, double e_mag) { return oc_mobility_of(p, 0, e_mag); }
 
 /* Eq. 6 along the z axis used here (negative: towards the pixel plane). */
 double oc_drift_field(const oc_params *p, double z)
@@ -175,9 +209,10 @@ double oc_drift_field(const oc_params *p, double z)
     return -((p->v_bias + p->v_dep) / H - 2.0 * p->v_dep * z / (H * H));
 }
 
-/* Eq. 4 field on carrier a from the n carriers in (x, y, z), skipping a. */
+/* Eq. 4 field on carrier a from the n carriers in (x, y, z) with charges q
+ * (+1 hole, -1 electron; NULL = all holes), skipping a. */
 static void repulsion_one(const oc_params *p, int64_t n, const double *x, const double *y,
-                          const double *z, int64_t a, double K, double E[3])
+                          const double *z, const double *q, int64_t a, double K, double E[3])
 {
     const double s2 = p->softening_um * p->softening_um;
     double ex = 0.0, ey = 0.0, ez = 0.0;
@@ -185,7 +220,7 @@ static void repulsion_one(const oc_params *p, int64_t n, const double *x, const 
         if (b == a) continue;
         const double dx = x[a] - x[b], dy = y[a] - y[b], dz = z[a] - z[b];
         const double r2 = dx * dx + dy * dy + dz * dz + s2;
-        const double inv_r3 = 1.0 / (r2 * sqrt(r2));
+        const double inv_r3 = (q ? q[b] : 1.0) / (r2 * sqrt(r2));
         ex += dx * inv_r3;
         ey += dy * inv_r3;
         ez += dz * inv_r3;
@@ -195,8 +230,9 @@ static void repulsion_one(const oc_params *p, int64_t n, const double *x, const 
     E[2] = K * ez;
 }
 
-/* Repulsion field of n carriers on each other ([n][3] in, [n][3] out). */
-void oc_field(const oc_params *p, int64_t n, const double *xyz, double *E)
+/* Field of n carriers with charges q (+1 / -1; NULL = all holes) on each
+ * other ([n][3] in, [n][3] out). */
+void oc_field_q(const oc_params *p, int64_t n, const double *xyz, const double *q, double *E)
 {
     double *x = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double *y = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
@@ -208,10 +244,16 @@ void oc_field(const oc_params *p, int64_t n, const double *xyz, double *E)
     }
     const double K = oc_coulomb_k(p);
 #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) repulsion_one(p, n, x, y, z, i, K, E + 3 * i);
+    for (int64_t i = 0; i < n; ++i) repulsion_one(p, n, x, y, z, q, i, K, E + 3 * i);
     free(x);
     free(y);
     free(z);
+}
+
+/* Repulsion field of n holes on each other ([n][3] in, [n][3] out). */
+void oc_field(const oc_params *p, int64_t n, const double *xyz, double *E)
+{
+    oc_field_q(p, n, xyz, NULL, E);
 }
 
 /* Repulsion field on selected carriers only: E[t] for carrier targets[t] of
@@ -229,17 +271,25 @@ void oc_field_targets(const oc_params *p, int64_t n, const double *xyz, int64_t 
     }
     const double K = oc_coulomb_k(p);
 #pragma omp parallel for schedule(static)
-    for (int64_t t = 0; t < n_t; ++t) repulsion_one(p, n, x, y, z, targets[t], K, E + 3 * t);
+    for (int64_t t = 0; t < n_t; ++t) repulsion_one(p, n, x, y, z, NULL, targets[t], K, E + 3 * t);
     free(x);
     free(y);
     free(z);
 }
 
-/* Algorithm 1, initialisation: N = round(E / w) carriers. */
+/* Algorithm 1, initialisation: N = round(E / w) holes. */
 int32_t oc_carrier_count(const oc_params *p, const oc_event *ev)
 {
     if (ev->n_carriers > 0) return ev->n_carriers;
     return (int32_t)floor(1000.0 * ev->energy_kev / p->pair_energy_ev + 0.5);
+}
+
+/* Electrons of an event: none without the electron species, else one per
+ * hole unless an explicit count is given. */
+int32_t oc_electron_count(const oc_params *p, const oc_event *ev)
+{
+    if (!(p->physics & OC_ELECTRONS)) return 0;
+    return ev->n_electrons >= 0 ? ev->n_electrons : oc_carrier_count(p, ev);
 }
 
 /* Eq. 2: sigma = 0.0044 E^1.75 (um, E in keV) unless the event states one. */
@@ -266,20 +316,23 @@ static int check_params(const oc_params *p)
         return OC_EINVAL;
     if (!(p->pair_energy_ev > 0.0) || p->mobility < 0 || p->mobility > 1) return OC_EINVAL;
     if ((p->physics & OC_DRIFT) && !(p->v_bias > p->v_dep && p->v_dep >= 0.0)) return OC_EINVAL;
-    double m[3];
-    oc_mobility_params(p, m);
-    if (!(m[0] > 0.0) || !(m[1] > 0.0) || !(m[2] > 0.0)) return OC_EINVAL;
+    if (p->physics & ~15u) return OC_EINVAL;
+    for (int e = 0; e < 2; ++e) {
+        double m[3];
+        oc_mobility_params_of(p, e, m);
+        if (!(m[0] > 0.0) || !(m[1] > 0.0) || !(m[2] > 0.0)) return OC_EINVAL;
+    }
     return OC_OK;
 }
 
 typedef struct {
-    int32_t n;
+    int32_t n, nh;  /* carriers; the first nh are holes, the rest electrons */
     double *x, *y, *z;
     double *nx, *ny, *nz;
     int32_t *id;
     unsigned char *alive;
     int64_t *act; /* indices of the alive carriers, in carrier order */
-    double *ax, *ay, *az;
+    double *ax, *ay, *az, *aq;
 } oc_work;
 
 static void retire(const oc_params *p, oc_work *w, int32_t i, int64_t step, int32_t *pix,
@@ -290,16 +343,31 @@ static void retire(const oc_params *p, oc_work *w, int32_t i, int64_t step, int3
     xyz_out[3 * i + 1] = w->y[i];
     xyz_out[3 * i + 2] = w->z[i];
     cstep[i] = (int32_t)step;
-    pix[oc_pixel_bin(p, w->x[i], w->y[i])] += 1;
+    if (i < w->nh) pix[oc_pixel_bin(p, w->x[i], w->y[i])] += 1;  /* holes reach the pixels */
+}
+
+/* Boundaries after an update: holes are mirrored at the entrance side and
+ * collected at the pixel plane; electrons are mirrored at the pixel plane
+ * and collected at the entrance side.  Returns 1 when collected. */
+static int boundary(const oc_work *w, int32_t i, double H, double *z)
+{
+    if (i < w->nh) {
+        if (*z > H) *z = 2.0 * H - *z;
+        return *z <= 0.0;
+    }
+    if (*z < 0.0) *z = -*z;
+    return *z >= H;
 }
 
 /* Simulate one event to completion (or max_steps).  Outputs are indexed by
- * the carrier's position in the event. */
+ * the carrier's position in the event: holes, then electrons. */
 static int run_event(const oc_params *p, const oc_event *ev, uint64_t eid, int parallel_targets,
                      int32_t *pix, double *xyz_out, int32_t *cstep, int64_t *steps_out,
                      uint64_t *pairs_out, uint64_t *hole_steps_out)
 {
-    const int32_t n = oc_carrier_count(p, ev);
+    const int32_t nh = oc_carrier_count(p, ev);
+    const int32_t ne = oc_electron_count(p, ev);
+    const int32_t n = (nh > 0 ? nh : 0) + (ne > 0 ? ne : 0);
     const double H = p->thickness_um;
     const double sigma = oc_initial_sigma(ev);
     const double K = oc_coulomb_k(p);
@@ -310,10 +378,12 @@ static int run_event(const oc_params *p, const oc_event *ev, uint64_t eid, int p
     *pairs_out = 0;
     *hole_steps_out = 0;
     if (n <= 0) return OC_OK;
+    if (ev->n_deposits > 0 && ne > 0 && ne != nh) return OC_EINVAL;
 
     oc_work w;
     const size_t nd = (size_t)n;
     w.n = n;
+    w.nh = nh > 0 ? nh : 0;
     w.x = malloc(nd * sizeof(double));
     w.y = malloc(nd * sizeof(double));
     w.z = malloc(nd * sizeof(double));
@@ -323,47 +393,58 @@ static int run_event(const oc_params *p, const oc_event *ev, uint64_t eid, int p
     w.ax = malloc(nd * sizeof(double));
     w.ay = malloc(nd * sizeof(double));
     w.az = malloc(nd * sizeof(double));
+    w.aq = malloc(nd * sizeof(double));
     w.id = malloc(nd * sizeof(int32_t));
     w.alive = malloc(nd);
     w.act = malloc(nd * sizeof(int64_t));
     int status = OC_OK;
 
-    /* initial cloud: Gaussian around each deposit (Algorithm 1, Eq. 2) */
+    /* initial cloud: Gaussian around each deposit (Algorithm 1, Eq. 2); the
+     * electron of a pair starts where its hole does */
     for (int32_t i = 0; i < n; ++i) {
-        w.id[i] = ev->ids ? ev->ids[i] : i;
+        const int32_t k = i < w.nh ? i : i - w.nh; /* index within the species */
+        w.id[i] = ev->ids ? ev->ids[i] : k;
         cstep[i] = -1;
         if (ev->n_deposits > 0) {
-            const double *d = ev->deposits + 3 * (i % ev->n_deposits);
-            double g[3];
-            oc_normals3(p->seed, (uint32_t)w.id[i], 0u, (uint32_t)eid, 1u, g);
-            w.x[i] = d[0] + sigma * g[0];
-            w.y[i] = d[1] + sigma * g[1];
-            w.z[i] = d[2] + sigma * g[2];
+            if (i < w.nh) {
+                const double *d = ev->deposits + 3 * (i % ev->n_deposits);
+                double g[3];
+                oc_normals3(p->seed, (uint32_t)w.id[i], 0u, (uint32_t)eid, 1u, g);
+                w.x[i] = d[0] + sigma * g[0];
+                w.y[i] = d[1] + sigma * g[1];
+                w.z[i] = d[2] + sigma * g[2];
+            } else {
+                w.x[i] = w.x[k];
+                w.y[i] = w.y[k];
+                w.z[i] = w.z[k];
+            }
         } else {
             w.x[i] = ev->xyz[3 * i];
             w.y[i] = ev->xyz[3 * i + 1];
             w.z[i] = ev->xyz[3 * i + 2];
             if (!isfinite(w.x[i]) || !isfinite(w.y[i]) || !isfinite(w.z[i])) status = OC_ENONFINITE;
         }
-        if (w.z[i] > H) w.z[i] = 2.0 * H - w.z[i];
         w.alive[i] = 1;
     }
     if (status != OC_OK) goto done;
     for (int32_t i = 0; i < n; ++i)
-        if (w.z[i] <= 0.0) retire(p, &w, i, ev->start_step, pix, xyz_out, cstep);
+        if (boundary(&w, i, H, &w.z[i])) retire(p, &w, i, ev->start_step, pix, xyz_out, cstep);
 
     int64_t step = ev->start_step;
     for (;;) {
-        /* snapshot of the alive set, in carrier order */
-        int64_t na = 0;
+        /* snapshot of the alive set, in carrier order; the event ends with
+         * its last hole */
+        int64_t na = 0, holes = 0;
         for (int32_t i = 0; i < n; ++i)
             if (w.alive[i]) {
                 w.ax[na] = w.x[i];
                 w.ay[na] = w.y[i];
                 w.az[na] = w.z[i];
+                w.aq[na] = i < w.nh ? 1.0 : -1.0;
                 w.act[na++] = i;
+                holes += i < w.nh;
             }
-        if (na == 0) break;
+        if (holes == 0) break;
         if (step - ev->start_step >= p->max_steps) {
             status = OC_EMAXSTEPS;
             break;
@@ -373,33 +454,37 @@ static int run_event(const oc_params *p, const oc_event *ev, uint64_t eid, int p
 #pragma omp parallel for schedule(static) if (parallel_targets)
         for (int64_t a = 0; a < na; ++a) {
             const int64_t i = w.act[a];
+            const int electron = i >= w.nh;
+            const double sign = electron ? -1.0 : 1.0; /* velocity along q_i E */
             double Er[3] = {0.0, 0.0, 0.0};
-            if (p->physics & OC_REPULSION) repulsion_one(p, na, w.ax, w.ay, w.az, a, K, Er);
+            if (p->physics & OC_REPULSION) repulsion_one(p, na, w.ax, w.ay, w.az, w.aq, a, K, Er);
             const double Ex = Er[0], Ey = Er[1], Ez = Er[2] + oc_drift_field(p, w.az[a]);
             const double Emag = sqrt(Ex * Ex + Ey * Ey + Ez * Ez);
-            const double mu = oc_mobility(p, Emag);
+            const double mu = oc_mobility_of(p, electron, Emag);
             double g[3] = {0.0, 0.0, 0.0};
             double hop = 0.0;
             if (p->physics & OC_DIFFUSION) {
                 const double D = mu * kT;
                 hop = sqrt(2.0 * D * dt);
-                oc_normals3(p->seed, (uint32_t)w.id[i], (uint32_t)step, (uint32_t)eid, 0u, g);
+                oc_normals3(p->seed, (uint32_t)w.id[i], (uint32_t)step, (uint32_t)eid,
+                            electron ? 4u : 0u, g);
             }
-            w.nx[i] = w.ax[a] + mu * Ex * dt + hop * g[0];
-            w.ny[i] = w.ay[a] + mu * Ey * dt + hop * g[1];
-            w.nz[i] = w.az[a] + mu * Ez * dt + hop * g[2];
+            w.nx[i] = w.ax[a] + sign * mu * Ex * dt + hop * g[0];
+            w.ny[i] = w.ay[a] + sign * mu * Ey * dt + hop * g[1];
+            w.nz[i] = w.az[a] + sign * mu * Ez * dt + hop * g[2];
         }
         step += 1;
         for (int64_t a = 0; a < na; ++a) {
             const int64_t i = w.act[a];
             w.x[i] = w.nx[i];
             w.y[i] = w.ny[i];
-            w.z[i] = w.nz[i] > H ? 2.0 * H - w.nz[i] : w.nz[i];
-            if (w.z[i] <= 0.0) retire(p, &w, (int32_t)i, step, pix, xyz_out, cstep);
+            w.z[i] = w.nz[i];
+            if (boundary(&w, (int32_t)i, H, &w.z[i]))
+                retire(p, &w, (int32_t)i, step, pix, xyz_out, cstep);
         }
     }
     *steps_out = step - ev->start_step;
-    /* carriers still alive report their current position */
+    /* carriers still drifting report their current position */
     for (int32_t i = 0; i < n; ++i)
         if (w.alive[i]) {
             xyz_out[3 * i] = w.x[i];
@@ -409,15 +494,17 @@ static int run_event(const oc_params *p, const oc_event *ev, uint64_t eid, int p
 done:
     free(w.x); free(w.y); free(w.z);
     free(w.nx); free(w.ny); free(w.nz);
-    free(w.ax); free(w.ay); free(w.az);
+    free(w.ax); free(w.ay); free(w.az); free(w.aq);
     free(w.id); free(w.alive); free(w.act);
     return status;
 }
 
 /* Run a batch.  Event b uses RNG event id first_event_id + b.  Outputs:
- * pix [B][grid_n^2 + 1], xyz_out [sum N_e][3], cstep [sum N_e] (-1 = alive),
+ * pix [B][grid_n^2 + 1] (holes), xyz_out [sum N_e][3], cstep [sum N_e]
+ * (-1 = still drifting), where N_e counts the event's holes and electrons,
  * steps [B], pairs = sum over steps of N_a (N_a - 1), hole_steps = sum over
- * steps of N_a.  Returns the worst status over events. */
+ * steps of N_a (carrier updates of both species).  Returns the worst status
+ * over events. */
 int oc_run(const oc_params *p, const oc_event *ev, int32_t n_events, uint64_t first_event_id,
            int32_t *pix, double *xyz_out, int32_t *cstep, int64_t *steps, uint64_t *pairs,
            uint64_t *hole_steps)
@@ -433,8 +520,8 @@ int oc_run(const oc_params *p, const oc_event *ev, int32_t n_events, uint64_t fi
             free(off);
             return OC_EINVAL;
         }
-        const int32_t n = oc_carrier_count(p, &ev[b]);
-        off[b + 1] = off[b] + (n > 0 ? n : 0);
+        const int32_t nh = oc_carrier_count(p, &ev[b]), ne = oc_electron_count(p, &ev[b]);
+        off[b + 1] = off[b] + (nh > 0 ? nh : 0) + (ne > 0 ? ne : 0);
     }
     int nthreads = 1;
 #ifdef _OPENMP

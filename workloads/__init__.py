@@ -11,7 +11,7 @@ from .events import (  # noqa: F401
     WORKLOADS,
     make_workload,
     single_8kev,
-    batch_8kev,
+    batch_8kev, batch_8kev_eh,
     mixed_energy,
     gamma_60kev,
     track_200kev,

@@ -46,6 +46,10 @@ class Sensor:
     mu0_override: float = math.nan  # um^2/(V ns); NaN = model value at T
     ec_override: float = math.nan  # V/um
     beta_override: float = math.nan
+    electrons: bool = False  # simulate the electron of every pair as well (two species)
+    mu0_e_override: float = math.nan  # electrons; NaN = model value at T
+    ec_e_override: float = math.nan
+    beta_e_override: float = math.nan
     repulsion: bool = True
     drift: bool = True
     diffusion: bool = True
@@ -61,13 +65,17 @@ class Batch:
     """A batch of events in flat arrays.
 
     energy_kev[b]   photon / particle energy (used when n_carriers[b] <= 0)
-    n_carriers[b]   carriers of event b; <= 0 means round(1000 E / w)
+    n_carriers[b]   holes of event b; <= 0 means round(1000 E / w)
+    n_electrons[b]  electrons of event b when the sensor simulates them:
+                    < 0 (cloud events) one per hole, starting where its hole
+                    starts; >= 0 (explicit events) that many positions follow
+                    the holes' in ``xyz``
     sigma_um[b]     per-axis Gaussian width around each deposit; < 0 means
                     the energy-dependent initial width of the paper (Eq. 2)
     n_deposits[b]   >= 1: Gaussian cloud(s) around the deposit points;
                     0: explicit carrier positions taken from ``xyz``
     deposits        [sum n_deposits, 3] deposit centres, in event order
-    xyz             [sum of carriers of explicit events, 3], in event order
+    xyz             [sum of explicit positions, 3], in event order
     start_step[b]   step index of the given state (0 for a fresh event)
     first_event_id  event b uses id first_event_id + b in the RNG counter
     """
@@ -81,6 +89,7 @@ class Batch:
     start_step: Optional[np.ndarray] = None
     first_event_id: int = 0
     name: str = ""
+    n_electrons: Optional[np.ndarray] = None
 
     def __post_init__(self):
         self.energy_kev = np.ascontiguousarray(self.energy_kev, dtype=np.float64)
@@ -94,12 +103,20 @@ class Batch:
         if self.start_step is None:
             self.start_step = np.zeros(B, dtype=np.int64)
         self.start_step = np.ascontiguousarray(self.start_step, dtype=np.int64).reshape(B)
+        if self.n_electrons is None:
+            self.n_electrons = np.where(self.n_deposits > 0, -1, 0)
+        self.n_electrons = np.ascontiguousarray(self.n_electrons, dtype=np.int32).reshape(B)
         if int(self.n_deposits.sum()) != self.deposits.shape[0]:
             raise ValueError("deposits rows must equal sum(n_deposits)")
 
     @property
     def n_events(self) -> int:
         return int(self.energy_kev.shape[0])
+
+    def explicit_rows(self) -> np.ndarray:
+        """Rows of ``xyz`` that each event owns (holes, then electrons)."""
+        return np.where(self.n_deposits == 0,
+                        self.n_carriers.astype(np.int64) + np.maximum(self.n_electrons, 0), 0)
 
     def dep_offsets(self) -> np.ndarray:
         off = np.zeros(self.n_events + 1, dtype=np.int64)
@@ -115,7 +132,7 @@ class Batch:
         doff = self.dep_offsets()
         xoff = None
         if self.xyz is not None:
-            nexp = np.where(self.n_deposits == 0, self.n_carriers, 0).astype(np.int64)
+            nexp = self.explicit_rows()
             xoff = np.zeros(self.n_events + 1, dtype=np.int64)
             np.cumsum(nexp, out=xoff[1:])
         out = []
@@ -129,7 +146,8 @@ class Batch:
                 sigma_um=self.sigma_um[b:b + 1], n_deposits=self.n_deposits[b:b + 1],
                 deposits=self.deposits[doff[b]:doff[b + 1]], xyz=xyz,
                 start_step=self.start_step[b:b + 1],
-                first_event_id=self.first_event_id + b, name=f"{self.name}[{b}]"))
+                first_event_id=self.first_event_id + b, name=f"{self.name}[{b}]",
+                n_electrons=self.n_electrons[b:b + 1]))
         return out
 
     def head(self, n: int) -> "Batch":
@@ -138,11 +156,12 @@ class Batch:
         doff = self.dep_offsets()
         xyz = None
         if self.xyz is not None:
-            nexp = int(np.where(self.n_deposits[:n] == 0, self.n_carriers[:n], 0).sum())
+            nexp = int(self.explicit_rows()[:n].sum())
             xyz = self.xyz[:nexp]
         return Batch(self.energy_kev[:n], self.n_carriers[:n], self.sigma_um[:n],
                      self.n_deposits[:n], self.deposits[:doff[n]], xyz,
-                     self.start_step[:n], self.first_event_id, f"{self.name}[:{n}]")
+                     self.start_step[:n], self.first_event_id, f"{self.name}[:{n}]",
+                     self.n_electrons[:n])
 
 
 # ---------------------------------------------------------------- samplers
@@ -264,14 +283,28 @@ def track_200kev(n_events: int = 16, seed: int = 0, n_segments: int = 40,
 
 
 def explicit_batch(xyz_per_event: Sequence[np.ndarray], first_event_id: int = 0,
-                   start_step: Optional[Sequence[int]] = None, name: str = "explicit") -> Batch:
-    """Events given by explicit carrier positions ([n_e, 3] each)."""
+                   start_step: Optional[Sequence[int]] = None, name: str = "explicit",
+                   electrons_per_event: Optional[Sequence[np.ndarray]] = None) -> Batch:
+    """Events given by explicit hole positions ([n_e, 3] each) and, for a
+    sensor that simulates electrons, explicit electron positions."""
     xs = [np.asarray(x, dtype=np.float64).reshape(-1, 3) for x in xyz_per_event]
     B = len(xs)
+    es = [np.zeros((0, 3))] * B if electrons_per_event is None else \
+        [np.asarray(x, dtype=np.float64).reshape(-1, 3) for x in electrons_per_event]
+    rows = [np.concatenate([h, e]) for h, e in zip(xs, es)]
     return Batch(energy_kev=np.zeros(B), n_carriers=[x.shape[0] for x in xs],
                  sigma_um=np.zeros(B), n_deposits=np.zeros(B), deposits=np.zeros((0, 3)),
-                 xyz=np.concatenate(xs) if xs else np.zeros((0, 3)),
-                 start_step=start_step, first_event_id=first_event_id, name=name)
+                 xyz=np.concatenate(rows) if rows else np.zeros((0, 3)),
+                 start_step=start_step, first_event_id=first_event_id, name=name,
+                 n_electrons=[e.shape[0] for e in es])
+
+
+def batch_8kev_eh(n_events: int = 256, seed: int = 0) -> tuple:
+    """batch_8kev with both species: 2222 holes and 2222 electrons per event,
+    each electron starting at its hole's position (4444 carriers)."""
+    s, b = batch_8kev(n_events=n_events, seed=seed)
+    b.name = "batch_8kev_eh"
+    return s.replace(electrons=True), b
 
 
 WORKLOADS: Dict[str, Callable[..., tuple]] = {
@@ -280,6 +313,7 @@ WORKLOADS: Dict[str, Callable[..., tuple]] = {
     "mixed_energy": mixed_energy,
     "gamma_60kev": gamma_60kev,
     "track_200kev": track_200kev,
+    "batch_8kev_eh": batch_8kev_eh,
 }
 
 
