@@ -103,7 +103,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    print(f"bench: {a.workload} {batch.n_events} events, {int(batch.n_carriers.sum())} holes; "
+    n_holes = int(batch.n_carriers.sum())
+    n_carriers = n_holes * (2 if sensor.electrons else 1)
+    species = "holes and electrons" if sensor.electrons else "holes"
+    print(f"bench: {a.workload} {batch.n_events} events, {n_carriers} carriers ({species}); "
           f"warmup {a.warmup}, steps {a.steps}", file=sys.stderr, flush=True)
     if a.copy_calibration_mb:
         n = a.copy_calibration_mb << 20
@@ -154,12 +157,12 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: {batch.n_events} events, "
-                               f"{int(batch.n_carriers.sum())} holes, "
+                               f"{n_carriers} carriers ({species}), "
                                f"{sensor.thickness_um:g} um Si at {sensor.v_bias:g} V, "
                                f"dt {sensor.dt_ns:g} ns; FP32 field, FP64 state; one "
                                f"persistent step kernel per run, events stepped "
                                f"independently through a device work queue",
-                   "events": batch.n_events, "holes": int(batch.n_carriers.sum()),
+                   "events": batch.n_events, "holes": n_holes, "carriers": n_carriers,
                    "launch": {"targets_per_thread": st.targets_per_thread,
                               "block": st.block_size, "chunk_len": st.chunk_len,
                               "workgroups": st.workgroups}},

@@ -16,6 +16,14 @@
  * (Eqs. 3 and 5).  Holes whose update leaves them at z <= 0 are collected
  * on the pixel plane and counted in a grid_n x grid_n pixel array.
  *
+ * With CT_ELECTRONS the electrons are simulated too (Sec. 2.1: both species
+ * as individual carriers, including electron-hole attraction).  Each source
+ * enters the sum with its sign (+1 hole, -1 electron); a hole moves along
+ * the total field, an electron against it with the Jacoboni-Canali electron
+ * mobility.  Electrons are collected at the entrance side (z >= H), mirrored
+ * at the pixel plane, and not counted in pixels.  An event ends when its
+ * last hole is collected; its electrons then keep their current position.
+ *
  * Units: micrometre, nanosecond, volt, kelvin.  z is the distance from the
  * pixel (collecting) plane; the paper's z (from the entrance side) is H - z.
  *
@@ -43,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CT_ABI_VERSION 1u
+#define CT_ABI_VERSION 2u
 
 typedef struct ct_ctx ct_ctx; /* opaque, owned by the library */
 
@@ -68,13 +76,15 @@ typedef enum {
 typedef enum { CT_FP64 = 0, CT_FP32 = 1 } ct_precision;
 
 /* Mobility model.  CT_MOB_JACOBONI: mu = mu0 / (1 + (E/Ec)^beta)^(1/beta),
- * with the Jacoboni-Canali hole laws at T (vm = 1.62e8 T^-0.52 cm/s,
- * Ec = 1.24 T^1.68 V/cm, beta = 0.46 T^0.17, mu0 = vm/Ec) unless overridden.
- * CT_MOB_CONSTANT: mu = mu0. */
+ * with the Jacoboni-Canali laws at T unless overridden, mu0 = vm/Ec:
+ *   holes:     vm = 1.62e8 T^-0.52 cm/s, Ec = 1.24 T^1.68 V/cm, beta = 0.46 T^0.17;
+ *   electrons: vm = 1.53e9 T^-0.87 cm/s, Ec = 1.01 T^1.55 V/cm, beta = 2.57e-2 T^0.66.
+ * CT_MOB_CONSTANT: mu = mu0 of the species. */
 typedef enum { CT_MOB_JACOBONI = 0, CT_MOB_CONSTANT = 1 } ct_mobility;
 
-/* physics_flags bits; the paper's method has all three on */
-enum { CT_REPULSION = 1u, CT_DRIFT = 2u, CT_DIFFUSION = 4u };
+/* physics_flags bits: repulsion, drift and diffusion are the paper's method;
+ * CT_ELECTRONS adds the electrons of every pair (two species) */
+enum { CT_REPULSION = 1u, CT_DRIFT = 2u, CT_DIFFUSION = 4u, CT_ELECTRONS = 8u };
 
 /* options bits */
 enum {
@@ -98,23 +108,31 @@ typedef struct {
     double eps_r;              /* relative permittivity > 0 (11.7 for silicon) */
     double pair_energy_ev;     /* energy per electron-hole pair > 0 (3.62 eV in the paper) */
     int32_t mobility;          /* ct_mobility */
-    double mu0_override;       /* um^2/(V ns); NaN = model value */
-    double ec_override;        /* V/um; NaN = model value */
-    double beta_override;      /* NaN = model value */
-    uint32_t physics_flags;    /* CT_REPULSION | CT_DRIFT | CT_DIFFUSION */
+    double mu0_override;       /* holes: um^2/(V ns); NaN = model value */
+    double ec_override;        /* holes: V/um; NaN = model value */
+    double beta_override;      /* holes: NaN = model value */
+    uint32_t physics_flags;    /* CT_REPULSION | CT_DRIFT | CT_DIFFUSION [| CT_ELECTRONS] */
     int32_t precision;         /* ct_precision */
     uint64_t seed;             /* Philox4x32-10 key = (low 32 bits, high 32 bits) */
     int64_t max_steps;         /* default step cap for ct_step (> 0) */
     void *hip_stream;          /* hipStream_t to issue work on (e.g. torch's); NULL = own stream */
     int32_t device;            /* HIP device ordinal; -1 = the current device */
     uint32_t options;          /* CT_OPT_* bits */
+    double mu0_e_override;     /* electrons (CT_ELECTRONS): um^2/(V ns); NaN = model value */
+    double ec_e_override;      /* electrons: V/um; NaN = model value */
+    double beta_e_override;    /* electrons: NaN = model value */
 } ct_sensor_params;
 
-/* One event.  Carrier k of the event is placed at deposit (k mod n_deposits)
- * plus sigma times three standard normals drawn from Philox counter
- * (id_k, 0, event id, 1); with n_deposits == 0 it is placed at xyz[k].
- * Positions above the entrance side (z > H) are mirrored to 2H - z; carriers
- * at z <= 0 are collected at step start_step. */
+/* One event.  Its carriers are its holes, then (with CT_ELECTRONS) its
+ * electrons.  Hole k is placed at deposit (k mod n_deposits) plus sigma
+ * times three standard normals drawn from Philox counter (id_k, 0, event id,
+ * 1); electron k of a cloud event starts at hole k's position.  With
+ * n_deposits == 0 the carriers are placed at xyz (holes, then electrons).
+ * Holes above the entrance side (z > H) are mirrored to 2H - z and holes at
+ * z <= 0 are collected at step start_step; electrons below the pixel plane
+ * are mirrored to -z and electrons at z >= H are collected at start_step.
+ * Diffusion draws use counter (id, step, event id, 0) for holes and
+ * (id, step, event id, 4) for electrons. */
 typedef struct {
     double energy_kev;         /* used when n_carriers <= 0 or sigma_um < 0 */
     int32_t n_carriers;        /* > 0, or <= 0 for round(1000 E / pair_energy_ev) (Algorithm 1) */
@@ -122,15 +140,19 @@ typedef struct {
     double sigma_um;           /* per-axis width >= 0, or < 0 for 0.0044 E^1.75 (Eq. 2) */
     const double *deposits;    /* host [n_deposits][3], x y z in um */
     const double *xyz;         /* host [n_carriers][3] when n_deposits == 0 */
-    const int32_t *ids;        /* host [n_carriers] RNG carrier ids, or NULL for 0..n-1 */
+    const int32_t *ids;        /* host [carriers] RNG carrier ids (holes, then electrons), or
+                                  NULL for 0..n-1 within each species */
     int64_t start_step;        /* absolute step of the given state (0 for a new event) */
+    int32_t n_electrons;       /* with CT_ELECTRONS: < 0 one per hole (cloud events; explicit
+                                  events then list n_carriers electrons), >= 0 that many; without
+                                  CT_ELECTRONS it must be <= 0 */
 } ct_event_desc;
 
 typedef struct {
     int64_t steps;             /* sum over ct_step calls of the most steps any event took */
     uint64_t pairs;            /* sum over steps and events of N_a (N_a - 1) */
-    int64_t n_total;           /* carriers in the batch */
-    int64_t n_active;          /* carriers still drifting */
+    int64_t n_total;           /* carriers in the batch (both species) */
+    int64_t n_active;          /* holes still drifting */
     int64_t field_launches;    /* runs of the step kernel timed (CT_OPT_TIMING); one per
                                   ct_step call unless its work queue filled up */
     double field_kernel_ms;    /* their summed duration, HIP events on the context's stream */
@@ -139,7 +161,8 @@ typedef struct {
     int32_t block_size;
     int32_t chunk_len;         /* source chunk length (ct_set_launch) */
     int32_t workgroups;        /* resident workgroups of the step kernel */
-    uint64_t hole_steps;       /* sum over steps and events of N_a (hole updates performed) */
+    uint64_t hole_steps;       /* sum over steps and events of N_a (carrier updates performed,
+                                  both species) */
 } ct_run_stats;
 
 /* Create a context for one sensor configuration on one gfx950 device.
@@ -147,8 +170,9 @@ typedef struct {
  * (CT_EDEVICE otherwise, also on a host without a GPU). */
 ct_status ct_init_sensor(const ct_sensor_params *p, ct_ctx **out);
 
-/* Carrier count of each event as the library derives it (Algorithm 1:
- * round(1000 E / w) when n_carriers <= 0).  Host only. */
+/* Carrier count of each event as the library derives it: its holes
+ * (Algorithm 1: round(1000 E / w) when n_carriers <= 0) plus, with
+ * CT_ELECTRONS, its electrons.  Host only. */
 ct_status ct_event_carriers(const ct_sensor_params *p, const ct_event_desc *ev, int32_t n_events,
                             int32_t *n_out);
 
@@ -183,6 +207,7 @@ ct_status ct_step(ct_ctx *c, int64_t max_steps, int64_t *steps_done, int64_t *n_
 
 /* Copy results to host arrays (each nullable):
  *   pixel_counts [B][grid_n*grid_n + 1]  collected holes per pixel, last = outside the grid
+ *                                         (electrons are never counted)
  *   xyz          [N_total][3]            position at collection, or current position if
  *                                         still drifting; events in order, carriers in
  *                                         their given order
@@ -192,9 +217,10 @@ ct_status ct_step(ct_ctx *c, int64_t max_steps, int64_t *steps_done, int64_t *n_
 ct_status ct_collect(ct_ctx *c, int32_t *pixel_counts, double *xyz, int32_t *collect_step,
                      int64_t *event_steps, ct_run_stats *stats);
 
-/* Repulsion field (V/um, Eq. 4) that the next step would apply, computed by
- * the same kernels and precision as ct_step, for every carrier of the batch
- * ([N_total][3], carrier order); drifting carriers only, NaN for collected. */
+/* Field of the other carriers (V/um, Eq. 4, each source with its sign) at
+ * every carrier, as the next step would use it, computed by the same
+ * kernels and precision as ct_step ([N_total][3], carrier order); drifting
+ * carriers only, NaN for collected. */
 ct_status ct_field(ct_ctx *c, double *field);
 
 /* Philox4x32-10 blocks and the Box-Muller normals the kernels derive from

@@ -27,11 +27,11 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 # kernels compiled with different tuning macros)
 LIB_PATH = os.environ.get("CT_LIBRARY") or os.path.join(_PKG, "libct.so")
 
-CT_ABI_VERSION = 1
+CT_ABI_VERSION = 2
 CT_OK, CT_EINVAL, CT_ESTATE, CT_ENOMEM, CT_EDEVICE, CT_EMAXSTEPS, CT_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 CT_FP64, CT_FP32 = 0, 1
 CT_MOB_JACOBONI, CT_MOB_CONSTANT = 0, 1
-CT_REPULSION, CT_DRIFT, CT_DIFFUSION = 1, 2, 4
+CT_REPULSION, CT_DRIFT, CT_DIFFUSION, CT_ELECTRONS = 1, 2, 4, 8
 CT_OPT_TIMING = 1
 CT_OPT_AUTOTUNE = 4
 
@@ -54,7 +54,8 @@ class ct_sensor_params(C.Structure):
         ("mu0_override", C.c_double), ("ec_override", C.c_double), ("beta_override", C.c_double),
         ("physics_flags", C.c_uint32), ("precision", C.c_int32), ("seed", C.c_uint64),
         ("max_steps", C.c_int64), ("hip_stream", C.c_void_p), ("device", C.c_int32),
-        ("options", C.c_uint32),
+        ("options", C.c_uint32), ("mu0_e_override", C.c_double), ("ec_e_override", C.c_double),
+        ("beta_e_override", C.c_double),
     ]
 
 
@@ -63,6 +64,7 @@ class ct_event_desc(C.Structure):
         ("energy_kev", C.c_double), ("n_carriers", C.c_int32), ("n_deposits", C.c_int32),
         ("sigma_um", C.c_double), ("deposits", C.POINTER(C.c_double)),
         ("xyz", C.POINTER(C.c_double)), ("ids", C.POINTER(C.c_int32)), ("start_step", C.c_int64),
+        ("n_electrons", C.c_int32),
     ]
 
 
@@ -136,14 +138,14 @@ def _dp(a):
 def make_params(sensor, precision: int = CT_FP64, stream=None, device: int = -1,
                 options: int = 0) -> ct_sensor_params:
     flags = (CT_REPULSION if sensor.repulsion else 0) | (CT_DRIFT if sensor.drift else 0) | \
-        (CT_DIFFUSION if sensor.diffusion else 0)
+        (CT_DIFFUSION if sensor.diffusion else 0) | (CT_ELECTRONS if sensor.electrons else 0)
     mob = {"jacoboni": CT_MOB_JACOBONI, "constant": CT_MOB_CONSTANT}[sensor.mobility]
     return ct_sensor_params(
         CT_ABI_VERSION, sensor.thickness_um, sensor.v_bias, sensor.v_dep, sensor.temperature_k,
         sensor.pitch_um, sensor.grid_n, sensor.dt_ns, sensor.softening_um, sensor.eps_r,
         sensor.pair_energy_ev, mob, sensor.mu0_override, sensor.ec_override, sensor.beta_override,
         flags, int(precision), int(sensor.seed), int(sensor.max_steps), stream, int(device),
-        int(options))
+        int(options), sensor.mu0_e_override, sensor.ec_e_override, sensor.beta_e_override)
 
 
 class EventDescs:
@@ -161,7 +163,7 @@ class EventDescs:
             dep = np.ascontiguousarray(batch.deposits[doff[b]:doff[b + 1]]) if nd > 0 else None
             xyz = None
             if nd == 0:
-                n = int(batch.n_carriers[b])
+                n = int(batch.n_carriers[b]) + max(int(batch.n_electrons[b]), 0)
                 xyz = np.ascontiguousarray(batch.xyz[xo:xo + n])
                 xo += n
             idp = None
@@ -172,7 +174,7 @@ class EventDescs:
             self._keep += [dep, xyz]
             self.arr[b] = ct_event_desc(float(batch.energy_kev[b]), int(batch.n_carriers[b]), nd,
                                         float(batch.sigma_um[b]), _dp(dep), _dp(xyz), idp,
-                                        int(batch.start_step[b]))
+                                        int(batch.start_step[b]), int(batch.n_electrons[b]))
 
 
 # ------------------------------------------------------------ wrappers

@@ -63,6 +63,20 @@ void hole_mobility_params(const ct_sensor_params &p, double &mu0, double &ec, do
     if (!std::isnan(p.beta_override)) beta = p.beta_override;
 }
 
+// Jacoboni-Canali electron parameters at T: vm = 1.53e9 T^-0.87 cm/s,
+// Ec = 1.01 T^1.55 V/cm, beta = 2.57e-2 T^0.66; mu0 = vm/Ec.
+void electron_mobility_params(const ct_sensor_params &p, double &mu0, double &ec, double &beta)
+{
+    const double T = p.temperature_k;
+    const double vm_um_ns = 1.53e9 * std::pow(T, -0.87) * 1e-5;
+    ec = 1.01 * std::pow(T, 1.55) * 1e-4;
+    beta = 2.57e-2 * std::pow(T, 0.66);
+    mu0 = vm_um_ns / ec;
+    if (!std::isnan(p.mu0_e_override)) mu0 = p.mu0_e_override;
+    if (!std::isnan(p.ec_e_override)) ec = p.ec_e_override;
+    if (!std::isnan(p.beta_e_override)) beta = p.beta_e_override;
+}
+
 ct_status check_params(const ct_sensor_params *p)
 {
     if (!p) return fail(CT_EINVAL, "params is NULL");
@@ -82,7 +96,7 @@ ct_status check_params(const ct_sensor_params *p)
         return fail(CT_EINVAL, "unknown mobility model %d", p->mobility);
     if (p->precision != CT_FP64 && p->precision != CT_FP32)
         return fail(CT_EINVAL, "unknown precision %d", p->precision);
-    if (p->physics_flags & ~7u) return fail(CT_EINVAL, "unknown physics flag bits");
+    if (p->physics_flags & ~15u) return fail(CT_EINVAL, "unknown physics flag bits");
     if ((p->physics_flags & CT_DRIFT) && !(p->v_bias > p->v_dep && p->v_dep >= 0.0))
         return fail(CT_EINVAL, "the linear drift field needs 0 <= v_dep < v_bias (Eq. 6)");
     if (p->max_steps <= 0) return fail(CT_EINVAL, "max_steps must be > 0");
@@ -92,6 +106,9 @@ ct_status check_params(const ct_sensor_params *p)
     hole_mobility_params(*p, mu0, ec, beta);
     if (!(mu0 > 0.0) || !(ec > 0.0) || !(beta > 0.0) || !std::isfinite(mu0))
         return fail(CT_EINVAL, "mobility parameters must be > 0");
+    electron_mobility_params(*p, mu0, ec, beta);
+    if (!(mu0 > 0.0) || !(ec > 0.0) || !(beta > 0.0) || !std::isfinite(mu0))
+        return fail(CT_EINVAL, "electron mobility parameters must be > 0");
     return CT_OK;
 }
 
@@ -110,6 +127,8 @@ ct::DevParams make_dev_params(const ct_sensor_params &p)
     d.s2f = (float)d.s2;
     hole_mobility_params(p, d.mu0, d.ec, d.beta);
     d.inv_beta = 1.0 / d.beta;
+    electron_mobility_params(p, d.mu0_e, d.ec_e, d.beta_e);
+    d.inv_beta_e = 1.0 / d.beta_e;
     d.pitch = p.pitch_um;
     d.half_width = 0.5 * p.grid_n * p.pitch_um;
     d.grid_n = p.grid_n;
@@ -120,6 +139,7 @@ ct::DevParams make_dev_params(const ct_sensor_params &p)
     return d;
 }
 
+// Holes of an event (Algorithm 1: round(1000 E / w) unless stated).
 int32_t carrier_count(const ct_sensor_params &p, const ct_event_desc &e)
 {
     if (e.n_carriers > 0) return e.n_carriers;
@@ -135,7 +155,7 @@ double initial_sigma(const ct_event_desc &e)
 
 // Byte layout of one batch inside a single device buffer.
 struct Layout {
-    size_t off, n_act, ev_step, ev_taken, call_steps, ref, pos, idx, nidx, rngid, out_xyz, out_cstep, pix,
+    size_t off, n_act, n_hole, nh0, ev_step, ev_taken, call_steps, ref, pos, idx, nidx, rngid, out_xyz, out_cstep, pix,
         pairs, hsteps, sigma, dep_off, deposits, x_off, xyz_in, start, total;
 };
 
@@ -152,6 +172,8 @@ Layout make_layout(int64_t B, int64_t N, int64_t n_dep, int64_t n_exp, int G1)
     };
     L.off = take(sizeof(int32_t) * (B + 1));
     L.n_act = take(sizeof(int32_t) * B);
+    L.n_hole = take(sizeof(int32_t) * B);
+    L.nh0 = take(sizeof(int32_t) * B);
     L.ev_step = take(sizeof(int64_t) * B);
     L.ev_taken = take(sizeof(int64_t) * B);
     L.call_steps = take(sizeof(int64_t) * B);
@@ -178,7 +200,8 @@ Layout make_layout(int64_t B, int64_t N, int64_t n_dep, int64_t n_exp, int G1)
 struct BatchShape {
     int64_t B = 0, N = 0, n_dep = 0, n_exp = 0;
     int32_t n_max = 0;
-    std::vector<int32_t> n;
+    std::vector<int32_t> n;   // carriers of each event (holes + electrons)
+    std::vector<int32_t> nh;  // holes of each event
 };
 
 ct_status shape_of(const ct_sensor_params &p, const ct_event_desc *ev, int32_t B, BatchShape &s)
@@ -188,19 +211,30 @@ ct_status shape_of(const ct_sensor_params &p, const ct_event_desc *ev, int32_t B
     s = BatchShape{};
     s.B = B;
     s.n.resize(B);
+    s.nh.resize(B);
+    const bool electrons = (p.physics_flags & CT_ELECTRONS) != 0;
     for (int32_t b = 0; b < B; ++b) {
         const ct_event_desc &e = ev[b];
         if (e.n_deposits < 0) return fail(CT_EINVAL, "event %d: n_deposits < 0", b);
-        if (e.n_deposits == 0 && e.n_carriers > 0 && !e.xyz)
-            return fail(CT_EINVAL, "event %d: explicit positions missing", b);
         if (e.n_deposits > 0 && !e.deposits) return fail(CT_EINVAL, "event %d: deposits missing", b);
         if ((e.n_carriers <= 0 || e.sigma_um < 0.0) && !(e.energy_kev > 0.0) && e.n_deposits > 0)
             return fail(CT_EINVAL, "event %d: energy needed for the carrier count or width", b);
         if (e.n_deposits == 0 && e.n_carriers <= 0 && e.energy_kev != 0.0)
             return fail(CT_EINVAL, "event %d: explicit events state n_carriers", b);
-        const int32_t n = carrier_count(p, e);
+        const int32_t nh = carrier_count(p, e);
         if (e.n_deposits > 0 && !std::isfinite(initial_sigma(e)))
             return fail(CT_EINVAL, "event %d: width not finite", b);
+        int32_t ne = 0;
+        if (electrons) ne = e.n_electrons >= 0 ? e.n_electrons : nh;
+        else if (e.n_electrons > 0)
+            return fail(CT_EINVAL, "event %d: electrons given without CT_ELECTRONS", b);
+        if (e.n_deposits > 0 && ne != 0 && ne != nh)
+            return fail(CT_EINVAL, "event %d: a cloud event has one electron per hole", b);
+        if ((int64_t)nh + ne > INT32_MAX / 2) return fail(CT_EINVAL, "event %d too large", b);
+        const int32_t n = nh + ne;
+        if (e.n_deposits == 0 && n > 0 && !e.xyz)
+            return fail(CT_EINVAL, "event %d: explicit positions missing", b);
+        s.nh[b] = nh;
         s.n[b] = n;
         s.N += n;
         s.n_max = std::max(s.n_max, n);
@@ -700,7 +734,8 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
                 xyz[3 * (size_t)x_off[b] + d] = v;
             }
         }
-        for (int32_t k = 0; k < n; ++k) rngid[off[b] + k] = e.ids ? e.ids[k] : k;
+        const int32_t nh = s.nh[b];
+        for (int32_t k = 0; k < n; ++k) rngid[off[b] + k] = e.ids ? e.ids[k] : (k < nh ? k : k - nh);
     }
     st = set_device(c);
     if (st != CT_OK) return st;
@@ -715,6 +750,8 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     bt.first_event_id = first_event_id;
     bt.off = at<int32_t>(w, L.off);
     bt.n_act = at<int32_t>(w, L.n_act);
+    bt.n_hole = at<int32_t>(w, L.n_hole);
+    bt.nh0 = at<int32_t>(w, L.nh0);
     bt.ev_step = at<int64_t>(w, L.ev_step);
     bt.ev_taken = at<int64_t>(w, L.ev_taken);
     bt.call_steps = at<int64_t>(w, L.call_steps);
@@ -756,6 +793,8 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     std::vector<int64_t> zeros64(s.B, 0);
     CT_HIP(up((void *)bt.off, off.data(), sizeof(int32_t) * (s.B + 1)));
     CT_HIP(up(bt.n_act, n_act.data(), sizeof(int32_t) * s.B));
+    CT_HIP(up(bt.n_hole, s.nh.data(), sizeof(int32_t) * s.B));
+    CT_HIP(up((void *)bt.nh0, s.nh.data(), sizeof(int32_t) * s.B));
     CT_HIP(up(bt.ev_step, start.data(), sizeof(int64_t) * s.B));
     CT_HIP(up(bt.ev_taken, zeros64.data(), sizeof(int64_t) * s.B));
     CT_HIP(up(bt.call_steps, zeros64.data(), sizeof(int64_t) * s.B));

@@ -15,12 +15,13 @@ struct DevParams {
     double K;          // e / (4 pi eps0 eps_r) (V um)
     double kT;         // k T / e (V)
     double s2;         // softening^2 (um^2), never below a tiny floor
-    double mu0, ec, beta, inv_beta;
+    double mu0, ec, beta, inv_beta;           // holes
+    double mu0_e, ec_e, beta_e, inv_beta_e;   // electrons
     double pitch, half_width;  // pixel pitch, grid_n * pitch / 2
     float s2f;
     int32_t grid_n;
     int32_t mobility;  // 0 Caughey-Thomas (Jacoboni-Canali), 1 constant
-    uint32_t flags;    // repulsion 1, drift 2, diffusion 4
+    uint32_t flags;    // repulsion 1, drift 2, diffusion 4, electrons 8
     uint32_t key0, key1;
 };
 
@@ -29,10 +30,10 @@ constexpr int kMaxChunks = 256;
 
 // One work item: target tile `tile` of event `e` (bs * kt targets) against
 // source chunk `chunk` of the same event, for the event's current step, in
-// which the event has `n` drifting holes (the item's split into tiles and
-// chunks follows from n alone).
+// which the event has `n` drifting carriers, the first `nh` of them holes
+// (the item's split into tiles and chunks follows from n alone).
 struct QItem {
-    int32_t e, tile, chunk, n;
+    int32_t e, tile, chunk, n, nh, pad[3];
 };
 
 // Control block of one run of the persistent step kernel.  Tickets index the
@@ -59,14 +60,18 @@ struct Sched {
 constexpr int kEventLine = 16;  // int32 words
 
 // Device view of a batch.  Slots [off[b], off[b] + n_act[b]) of the position
-// arrays hold the drifting holes of event b, compacted and in carrier order;
-// slots [off[b], off[b + 1]) belong to event b for the whole run.
+// arrays hold the drifting carriers of event b, compacted and in carrier
+// order: its n_hole[b] drifting holes first, then its drifting electrons
+// (carrier indices below nh0[b] are holes).  Slots [off[b], off[b + 1])
+// belong to event b for the whole run.
 struct DevBatch {
     int32_t n_events;
     int32_t n_total;
     uint64_t first_event_id;
     const int32_t *off;     // [B + 1] first slot of each event
-    int32_t *n_act;         // [B] drifting holes
+    int32_t *n_act;         // [B] drifting carriers
+    int32_t *n_hole;        // [B] drifting holes (the first n_hole of the n_act slots)
+    const int32_t *nh0;     // [B] holes of the event (carrier indices below are holes)
     int64_t *ev_step;       // [B] absolute step of the event
     int64_t *ev_taken;      // [B] steps taken since seeding
     int64_t *call_steps;    // [B] steps taken in the current ct_step call

@@ -29,7 +29,8 @@ namespace ct {
 
 namespace {
 
-constexpr uint32_t kDomainDiffusion = 0u;
+constexpr uint32_t kDomainDiffusion = 0u;           // holes
+constexpr uint32_t kDomainDiffusionElectron = 4u;
 constexpr uint32_t kDomainCloud = 1u;
 
 // ------------------------------------------------------------------ Philox
@@ -137,10 +138,27 @@ __device__ __forceinline__ bool dec_is_last(int32_t *p)
 
 // ------------------------------------------------------------------ physics
 
-__device__ __forceinline__ double mobility(const DevParams &dp, double e_mag)
+__device__ __forceinline__ double mobility(const DevParams &dp, bool electron, double e_mag)
 {
-    if (dp.mobility == 1) return dp.mu0;
-    return dp.mu0 / pow(1.0 + pow(e_mag / dp.ec, dp.beta), dp.inv_beta);
+    const double mu0 = electron ? dp.mu0_e : dp.mu0;
+    if (dp.mobility == 1) return mu0;
+    const double ec = electron ? dp.ec_e : dp.ec;
+    const double beta = electron ? dp.beta_e : dp.beta;
+    const double inv_beta = electron ? dp.inv_beta_e : dp.inv_beta;
+    return mu0 / pow(1.0 + pow(e_mag / ec, beta), inv_beta);
+}
+
+// Boundaries after a move: holes are mirrored at the entrance side and
+// collected at the pixel plane; electrons are mirrored at the pixel plane and
+// collected at the entrance side.  Returns true when collected.
+__device__ __forceinline__ bool boundary(const DevParams &dp, bool electron, double &z)
+{
+    if (!electron) {
+        if (z > dp.H) z = 2.0 * dp.H - z;
+        return z <= 0.0;
+    }
+    if (z < 0.0) z = -z;
+    return z >= dp.H;
 }
 
 __device__ __forceinline__ int pixel_bin(const DevParams &dp, double x, double y)
@@ -152,44 +170,52 @@ __device__ __forceinline__ int pixel_bin(const DevParams &dp, double x, double y
     return G * G;
 }
 
-__device__ void collect(const DevParams &dp, const DevBatch &bt, int b, int carrier, double x,
-                        double y, double z, int64_t step)
+// A carrier reaches an electrode: endpoint and step by carrier; holes are
+// counted in the pixel grid (with an overflow bin), electrons are not.
+__device__ void collect(const DevParams &dp, const DevBatch &bt, int b, int carrier, bool electron,
+                        double x, double y, double z, int64_t step)
 {
     bt.out_xyz[3 * (int64_t)carrier + 0] = x;
     bt.out_xyz[3 * (int64_t)carrier + 1] = y;
     bt.out_xyz[3 * (int64_t)carrier + 2] = z;
     bt.out_cstep[carrier] = (int32_t)step;
+    if (electron) return;
     const int g1 = dp.grid_n * dp.grid_n + 1;
     atomicAdd(&bt.pix[(int64_t)b * g1 + pixel_bin(dp, x, y)], 1);
 }
 
-// Update of one drifting hole (Eqs. 3, 5, 6 and Algorithm 1): E_rep is the
-// repulsion field at the step-start snapshot, already scaled by K.
+// Update of one drifting carrier (Eqs. 3, 5, 6 and Algorithm 1): (ex, ey,
+// ez_rep) is the field of the other carriers at the step-start snapshot,
+// already scaled by K.  A hole moves along the total field, an electron
+// against it, each with its own mobility at the total field's magnitude.
 __device__ void advance(const DevParams &dp, const DevBatch &bt, int b, int slot, double ex,
                         double ey, double ez_rep, int64_t step, uint32_t eid)
 {
     const double x = bt.cx[slot], y = bt.cy[slot], z = bt.cz[slot];
     const int k = bt.idx[slot];
     const int carrier = bt.off[b] + k;
+    const bool electron = k >= bt.nh0[b];
     double ez = ez_rep;
     if (dp.flags & 2u) ez += -(dp.e0 - dp.e1 * z);
     const double e_mag = sqrt(ex * ex + ey * ey + ez * ez);
-    const double mu = mobility(dp, e_mag);
+    const double mu = mobility(dp, electron, e_mag);
+    const double sm = electron ? -mu : mu;  // signed mobility
     double g[3] = {0.0, 0.0, 0.0};
     double hop = 0.0;
     if (dp.flags & 4u) {
         hop = sqrt(2.0 * (mu * dp.kT) * dp.dt);
-        normals3(dp, Ctr{(uint32_t)bt.rngid[carrier], (uint32_t)step, eid, kDomainDiffusion}, g);
+        normals3(dp, Ctr{(uint32_t)bt.rngid[carrier], (uint32_t)step, eid,
+                         electron ? kDomainDiffusionElectron : kDomainDiffusion}, g);
     }
-    const double x1 = x + mu * ex * dp.dt + hop * g[0];
-    const double y1 = y + mu * ey * dp.dt + hop * g[1];
-    double z1 = z + mu * ez * dp.dt + hop * g[2];
-    if (z1 > dp.H) z1 = 2.0 * dp.H - z1;  // mirror at the entrance side
+    const double x1 = x + sm * ex * dp.dt + hop * g[0];
+    const double y1 = y + sm * ey * dp.dt + hop * g[1];
+    double z1 = z + sm * ez * dp.dt + hop * g[2];
+    const bool done = boundary(dp, electron, z1);
     st_dev(&bt.nx[slot], x1);
     st_dev(&bt.ny[slot], y1);
     st_dev(&bt.nz[slot], z1);
     st_dev(&bt.nidx[slot], k);
-    if (z1 <= 0.0) collect(dp, bt, b, carrier, x1, y1, z1, step + 1);
+    if (done) collect(dp, bt, b, carrier, electron, x1, y1, z1, step + 1);
 }
 
 __device__ __forceinline__ void field_or_advance(const DevParams &dp, const DevBatch &bt, int b,
@@ -278,29 +304,31 @@ __device__ __forceinline__ void pair_f64(const D4 &s, double s2, const double (&
 
 // ------------------------------------------------------------ compaction
 
-// Holes of event b with z > 0 after the step survive; they are packed to the
-// front of the event's slots in carrier order by the NT threads of one
-// workgroup, from the post-step arrays (nx, ny, nz, nidx) into the current
-// ones (cx, cy, cz, idx).  Windows of kCompactChunks chunks of NT slots:
+// Carriers of event b still drifting after the step (holes: z > 0, the
+// first nh of the n slots; electrons: z < H) are packed to the front of the
+// event's slots in carrier order by the NT threads of one workgroup, from the
+// post-step arrays (nx, ny, nz, nidx) into the current ones (cx, cy, cz,
+// idx); surviving holes therefore stay ahead of surviving electrons.  Windows of kCompactChunks chunks of NT slots:
 // every z of a window is loaded at once, each wave ranks its survivors with
 // a 64-bit ballot and mbcnt per chunk, one barrier publishes the wave totals,
 // and the survivors are copied with independent loads and stores, so about
 // two memory latencies are exposed per window.  n is the event's count
-// before the step.  Thread 0 stores the new count and centroid (summed in a
-// fixed order) and, for a step, counts it.  Returns the survivors (in every
-// thread); ends with a barrier.
+// before the step.  Thread 0 stores the new counts (all, holes) and the
+// centroid (summed in a fixed order) and, for a step, counts it.  Returns the
+// survivors (in every thread) and, in thread 0, the surviving holes; ends
+// with a barrier.
 constexpr int kCompactChunks = 8;
 
 template <int NT>
-__device__ int compact_event(const DevBatch &bt, int b, int n, int count_step, int *wcount,
-                             double *wsum)
+__device__ int compact_event(const DevBatch &bt, int b, int n, int nh, double H, int count_step,
+                             int *wcount, double *wsum, int &holes_kept)
 {
     constexpr int W = NT / 64;
     constexpr int K = kCompactChunks;
     const int base = bt.off[b];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    int kept = 0;
+    int kept = 0, my_holes = 0;
     double sx = 0.0, sy = 0.0, sz = 0.0;
     for (int w0 = 0; w0 < n; w0 += K * NT) {
         double z[K];
@@ -313,7 +341,9 @@ __device__ int compact_event(const DevBatch &bt, int b, int n, int count_step, i
         int rank[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const bool a = z[j] > 0.0;
+            const int i = w0 + j * NT + tid;
+            const bool a = i < nh ? z[j] > 0.0 : (i < n && z[j] < H);
+            my_holes += (a && i < nh) ? 1 : 0;
             const uint64_t mask = __ballot(a);
             rank[j] = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -353,20 +383,26 @@ __device__ int compact_event(const DevBatch &bt, int b, int n, int count_step, i
         sx += __shfl_down(sx, o);
         sy += __shfl_down(sy, o);
         sz += __shfl_down(sz, o);
+        my_holes += __shfl_down(my_holes, o);
     }
     if (lane == 0) {
         wsum[0 * W + wave] = sx;
         wsum[1 * W + wave] = sy;
         wsum[2 * W + wave] = sz;
+        wcount[wave] = my_holes;
     }
     __syncthreads();
     if (tid == 0) {
         double X = 0.0, Y = 0.0, Z = 0.0;
+        int holes = 0;
         for (int q = 0; q < W; ++q) {
             X += wsum[0 * W + q];
             Y += wsum[1 * W + q];
             Z += wsum[2 * W + q];
+            holes += wcount[q];
         }
+        holes_kept = holes;
+        st_dev(&bt.n_hole[b], holes);
         if (kept > 0) {
             st_dev(&bt.ref[4 * b + 0], X / kept);
             st_dev(&bt.ref[4 * b + 1], Y / kept);
@@ -460,6 +496,7 @@ __device__ int claim(const DevQueue &dq, uint32_t n_events, uint64_t idle_ticks,
     out.tile = (int32_t)ld_relaxed(w + 1);
     out.chunk = (int32_t)ld_relaxed(w + 2);
     out.n = (int32_t)ld_relaxed(w + 3);
+    out.nh = (int32_t)ld_relaxed(w + 4);
     return 1;
 }
 
@@ -473,7 +510,7 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
     __shared__ int s_go;
     __shared__ int s_wcount[kCompactChunks * W];
     __shared__ double s_wsum[3 * W];
-    __shared__ int s_items, s_tiles, s_chunks;
+    __shared__ int s_items, s_tiles, s_chunks, s_nh;
     __shared__ uint32_t s_t0;
     const int tid = threadIdx.x;
     Sched *sc = dq.sc;
@@ -492,6 +529,7 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
         const QItem it = s_item;
         const int b = it.e;
         const int n = it.n;
+        const int nh = it.nh;  // the first nh slots hold holes, the rest electrons
         const int base = bt.off[b];
         const int n0 = bt.off[b + 1] - base;
         int len = n, chunks = 1;
@@ -521,26 +559,32 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
                         tx[m] = ty[m] = tz[m] = 0.0f;
                     }
                 }
-                for (int s0 = sb; s0 < se; s0 += BS) {
-                    __syncthreads();
-                    const int j = s0 + tid;
-                    float4 v = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
-                    if (j < se)
-                        v = make_float4((float)(bt.cx[base + j] - rx), (float)(bt.cy[base + j] - ry),
-                                        (float)(bt.cz[base + j] - rz), 0.0f);
-                    tile[tid] = v;
-                    __syncthreads();
-                    if (!wave_has_targets) continue;
-                    const int cnt = (min(BS, se - s0) + CT_PAIR_UNROLL - 1) / CT_PAIR_UNROLL * CT_PAIR_UNROLL;
-                    float ax[KT], ay[KT], az[KT];
+                // the chunk's holes add, its electrons subtract (q_j = +1 / -1)
+                for (int seg = 0; seg < 2; ++seg) {
+                    const int a0 = seg == 0 ? sb : max(sb, nh);
+                    const int a1 = seg == 0 ? min(se, nh) : se;
+                    const double sgn = seg == 0 ? 1.0 : -1.0;
+                    for (int s0 = a0; s0 < a1; s0 += BS) {
+                        __syncthreads();
+                        const int j = s0 + tid;
+                        float4 v = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
+                        if (j < a1)
+                            v = make_float4((float)(bt.cx[base + j] - rx), (float)(bt.cy[base + j] - ry),
+                                            (float)(bt.cz[base + j] - rz), 0.0f);
+                        tile[tid] = v;
+                        __syncthreads();
+                        if (!wave_has_targets) continue;
+                        const int cnt = (min(BS, a1 - s0) + CT_PAIR_UNROLL - 1) / CT_PAIR_UNROLL * CT_PAIR_UNROLL;
+                        float ax[KT], ay[KT], az[KT];
 #pragma unroll
-                    for (int m = 0; m < KT; ++m) ax[m] = ay[m] = az[m] = 0.0f;
-                    pairs_f32<KT>(tile, cnt, dp.s2f, tx, ty, tz, ax, ay, az);
+                        for (int m = 0; m < KT; ++m) ax[m] = ay[m] = az[m] = 0.0f;
+                        pairs_f32<KT>(tile, cnt, dp.s2f, tx, ty, tz, ax, ay, az);
 #pragma unroll
-                    for (int m = 0; m < KT; ++m) {  // fold the tile's FP32 partial into FP64
-                        ex[m] += (double)ax[m];
-                        ey[m] += (double)ay[m];
-                        ez[m] += (double)az[m];
+                        for (int m = 0; m < KT; ++m) {  // fold the tile's FP32 partial into FP64
+                            ex[m] += sgn * (double)ax[m];
+                            ey[m] += sgn * (double)ay[m];
+                            ez[m] += sgn * (double)az[m];
+                        }
                     }
                 }
             } else {
@@ -558,20 +602,35 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
                     }
                 }
                 const double s2 = dp.s2;
-                for (int s0 = sb; s0 < se; s0 += BS) {
-                    __syncthreads();
-                    const int j = s0 + tid;
-                    if (j < se) tile[tid] = D4{bt.cx[base + j], bt.cy[base + j], bt.cz[base + j], 0.0};
-                    __syncthreads();
-                    if (!wave_has_targets) continue;
-                    const int cnt = min(BS, se - s0);
-                    const int cnt4 = cnt & ~3;
-                    for (int j0 = 0; j0 < cnt4; j0 += 4) {
+                // the chunk's holes add, its electrons subtract (q_j = +1 / -1)
+                for (int seg = 0; seg < 2; ++seg) {
+                    const int a0 = seg == 0 ? sb : max(sb, nh);
+                    const int a1 = seg == 0 ? min(se, nh) : se;
+                    const double sgn = seg == 0 ? 1.0 : -1.0;
+                    double ax[KT], ay[KT], az[KT];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            pair_f64<KT>(tile[j0 + u], s2, tx, ty, tz, ex, ey, ez);
+                    for (int m = 0; m < KT; ++m) ax[m] = ay[m] = az[m] = 0.0;
+                    for (int s0 = a0; s0 < a1; s0 += BS) {
+                        __syncthreads();
+                        const int j = s0 + tid;
+                        if (j < a1) tile[tid] = D4{bt.cx[base + j], bt.cy[base + j], bt.cz[base + j], 0.0};
+                        __syncthreads();
+                        if (!wave_has_targets) continue;
+                        const int cnt = min(BS, a1 - s0);
+                        const int cnt4 = cnt & ~3;
+                        for (int j0 = 0; j0 < cnt4; j0 += 4) {
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                pair_f64<KT>(tile[j0 + u], s2, tx, ty, tz, ax, ay, az);
+                        }
+                        for (int jj = cnt4; jj < cnt; ++jj) pair_f64<KT>(tile[jj], s2, tx, ty, tz, ax, ay, az);
                     }
-                    for (int jj = cnt4; jj < cnt; ++jj) pair_f64<KT>(tile[jj], s2, tx, ty, tz, ex, ey, ez);
+#pragma unroll
+                    for (int m = 0; m < KT; ++m) {
+                        ex[m] += sgn * ax[m];
+                        ey[m] += sgn * ay[m];
+                        ez[m] += sgn * az[m];
+                    }
                 }
             }
         }
@@ -624,11 +683,13 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
             if (tid == 0) add_relaxed(&sc->done.v, 1u);
             continue;
         }
-        const int kept = compact_event<BS>(bt, b, n, 1, s_wcount, s_wsum);
+        int holes_kept = 0;
+        const int kept = compact_event<BS>(bt, b, n, nh, dp.H, 1, s_wcount, s_wsum, holes_kept);
         if (tid == 0) {
             int items = 0, tiles = 0, nchunk = 1;
             uint32_t t0q = 0;
-            if (kept > 0 && bt.call_steps[b] < ra.max_steps) {
+            // the event ends with its last hole (electrons may still drift)
+            if (holes_kept > 0 && bt.call_steps[b] < ra.max_steps) {
                 tiles = (kept + T - 1) / T;
                 int l2 = kept;
                 if (repulsion) event_chunks(kept, BS, ra.chunk, l2, nchunk);
@@ -643,6 +704,7 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
             s_items = items;
             s_tiles = tiles;
             s_chunks = nchunk;
+            s_nh = holes_kept;
             s_t0 = t0q;
         }
         __syncthreads();
@@ -659,6 +721,7 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
                 st_dev(w + 1, i / nchunk);
                 st_dev(w + 2, i % nchunk);
                 st_dev(w + 3, kept);
+                st_dev(w + 4, s_nh);
             }
             wait_own_stores();
             __syncthreads();
@@ -711,7 +774,7 @@ __global__ __launch_bounds__(1024) void k_init(DevBatch bt, DevQueue dq, int T, 
         int items = 0, nchunk = 1;
         if (e < B) {
             const int n = bt.n_act[e];
-            if (n > 0 && (field_only || bt.call_steps[e] < max_steps)) {
+            if (bt.n_hole[e] > 0 && (field_only || bt.call_steps[e] < max_steps)) {
                 const int tiles = (n + T - 1) / T;
                 int len = n;
                 if (repulsion) event_chunks(n, bs, chunk, len, nchunk);
@@ -747,7 +810,7 @@ __global__ __launch_bounds__(1024) void k_init(DevBatch bt, DevQueue dq, int T, 
                 continue;
             }
             for (int i = lane; i < ni; i += 64) {
-                dq.q[b0 + i] = QItem{e0 + k, i / nc, i % nc, bt.n_act[e0 + k]};
+                dq.q[b0 + i] = QItem{e0 + k, i / nc, i % nc, bt.n_act[e0 + k], bt.n_hole[e0 + k], {0, 0, 0}};
                 dq.seq[b0 + i] = dq.gen;
             }
         }
@@ -773,7 +836,7 @@ __global__ __launch_bounds__(1024) void k_summary(DevBatch bt, Sched *sc)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int64_t sum = 0, mx = 0;
     for (int e = tid; e < bt.n_events; e += 1024) {
-        sum += bt.n_act[e];
+        sum += bt.n_hole[e];
         mx = max(mx, bt.call_steps[e]);
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -798,11 +861,13 @@ __global__ __launch_bounds__(1024) void k_summary(DevBatch bt, Sched *sc)
 
 // Compaction of every event at seeding (holes already at z <= 0 are out),
 // which also sets the FP32 reference points.  One workgroup per event.
-__global__ __launch_bounds__(256) void k_compact(DevBatch bt)
+__global__ __launch_bounds__(256) void k_compact(DevParams dp, DevBatch bt)
 {
     __shared__ int wcount[kCompactChunks * 4];
     __shared__ double wsum[12];
-    compact_event<256>(bt, blockIdx.x, bt.n_act[blockIdx.x], 0, wcount, wsum);
+    int holes = 0;
+    compact_event<256>(bt, blockIdx.x, bt.n_act[blockIdx.x], bt.nh0[blockIdx.x], dp.H, 0, wcount,
+                       wsum, holes);
 }
 
 // Initial clouds (Algorithm 1, initialisation; Eq. 2 width).  One thread per
@@ -819,12 +884,16 @@ __global__ __launch_bounds__(256) void k_seed(DevParams dp, DevBatch bt)
     }
     const int b = lo;
     const int k = g - bt.off[b];
+    const bool electron = k >= bt.nh0[b];
     double x, y, z;
     const int d0 = bt.dep_off[b], nd = bt.dep_off[b + 1] - d0;
     if (nd > 0) {
-        const double *d = bt.deposits + 3 * (int64_t)(d0 + k % nd);
+        // electron k of a cloud event starts where hole k starts: same draw
+        const int kh = electron ? k - bt.nh0[b] : k;
+        const double *d = bt.deposits + 3 * (int64_t)(d0 + kh % nd);
         double n3[3];
-        normals3(dp, Ctr{(uint32_t)bt.rngid[g], 0u, (uint32_t)(bt.first_event_id + b), kDomainCloud},
+        normals3(dp, Ctr{(uint32_t)bt.rngid[bt.off[b] + kh], 0u, (uint32_t)(bt.first_event_id + b),
+                         kDomainCloud},
                  n3);
         const double sg = bt.sigma[b];
         x = d[0] + sg * n3[0];
@@ -836,16 +905,16 @@ __global__ __launch_bounds__(256) void k_seed(DevParams dp, DevBatch bt)
         y = p[1];
         z = p[2];
     }
-    if (z > dp.H) z = 2.0 * dp.H - z;
+    const bool done = boundary(dp, electron, z);
     bt.nidx[g] = k;
     bt.nx[g] = x;
     bt.ny[g] = y;
     bt.nz[g] = z;
     bt.out_cstep[g] = -1;
-    if (z <= 0.0) collect(dp, bt, b, g, x, y, z, bt.start[b]);
+    if (done) collect(dp, bt, b, g, electron, x, y, z, bt.start[b]);
 }
 
-// Current positions of drifting holes into the carrier-ordered output.
+// Current positions of drifting carriers into the carrier-ordered output.
 __global__ __launch_bounds__(256) void k_scatter_alive(DevBatch bt)
 {
     const int b = blockIdx.y;
@@ -935,9 +1004,8 @@ hipError_t launch_seed(const DevParams &dp, const DevBatch &bt, hipStream_t s)
 
 hipError_t launch_compact(const DevParams &dp, const DevBatch &bt, hipStream_t s)
 {
-    (void)dp;
     if (bt.n_events <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_compact, dim3(bt.n_events), dim3(256), 0, s, bt);
+    hipLaunchKernelGGL(k_compact, dim3(bt.n_events), dim3(256), 0, s, dp, bt);
     return hipGetLastError();
 }
 
