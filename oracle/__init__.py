@@ -20,7 +20,7 @@ _SRC = os.path.join(_HERE, "ct_oracle.c")
 _LIB = os.path.join(_HERE, "libct_oracle.so")
 
 OK, EINVAL, EMAXSTEPS, ENONFINITE = 0, -1, -5, -6
-REPULSION, DRIFT, DIFFUSION, ELECTRONS = 1, 2, 4, 8
+REPULSION, DRIFT, DIFFUSION, ELECTRONS, SPHERICAL = 1, 2, 4, 8, 16
 
 
 def build(force: bool = True) -> str:
@@ -76,6 +76,7 @@ def lib():
         L.oc_mobility_params_of.argtypes = [C.POINTER(OcParams), C.c_int, dp]
         L.oc_mobility_of.argtypes = [C.POINTER(OcParams), C.c_int, C.c_double]
         L.oc_mobility_of.restype = C.c_double
+        L.oc_field_spherical.argtypes = [C.POINTER(OcParams), C.c_int64, dp, dp]
         L.oc_field_q.argtypes = [C.POINTER(OcParams), C.c_int64, dp, dp, dp]
         L.oc_electron_count.argtypes = [C.POINTER(OcParams), C.POINTER(OcEvent)]
         L.oc_electron_count.restype = C.c_int32
@@ -108,7 +109,8 @@ def _dp(a: Optional[np.ndarray]):
 
 def params(sensor) -> OcParams:
     flags = (REPULSION if sensor.repulsion else 0) | (DRIFT if sensor.drift else 0) | \
-            (DIFFUSION if sensor.diffusion else 0) | (ELECTRONS if sensor.electrons else 0)
+            (DIFFUSION if sensor.diffusion else 0) | (ELECTRONS if sensor.electrons else 0) | \
+            (SPHERICAL if sensor.spherical else 0)
     mob = {"jacoboni": 0, "constant": 1}[sensor.mobility]
     return OcParams(sensor.thickness_um, sensor.v_bias, sensor.v_dep, sensor.temperature_k,
                     sensor.pitch_um, sensor.grid_n, sensor.dt_ns, sensor.softening_um, sensor.eps_r,
@@ -180,6 +182,15 @@ def field_q(sensor, xyz: np.ndarray, q: np.ndarray) -> np.ndarray:
     q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
     E = np.zeros_like(xyz)
     lib().oc_field_q(C.byref(params(sensor)), xyz.shape[0], _dp(xyz), _dp(q), _dp(E))
+    return E
+
+
+def field_spherical(sensor, xyz: np.ndarray) -> np.ndarray:
+    """Eq. 7 field (V/um) of the holes at xyz [n, 3] on each other: the holes
+    strictly closer to their mean position, concentrated there."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    E = np.zeros_like(xyz)
+    lib().oc_field_spherical(C.byref(params(sensor)), xyz.shape[0], _dp(xyz), _dp(E))
     return E
 
 

@@ -35,6 +35,14 @@
  *    in pixels.  An event ends when its last hole is collected (Algorithm 1:
  *    "until all holes reach the readout electrode"); electrons still
  *    drifting then keep their current position.
+ *  - Simplified spherical model (optional, physics bit 4; Sec. 2.2, Eq. 7):
+ *    the repulsion field at hole i is that of the holes strictly closer to
+ *    the cloud centre c than i, as if concentrated at c:
+ *        E_i = K Q_i (r_i - c) / (|r_i - c|^2 + s^2)^(3/2),
+ *        Q_i = #{ j drifting : |r_j - c|^2 < |r_i - c|^2 },
+ *    with c the mean position of the drifting holes at the step start; a
+ *    hole at the same distance as i does not count, and Q_i = 0 gives
+ *    E_i = 0.  Holes only (the model updates hole coordinates only).
  *  - Drift field (Eq. 6, rewritten for this z axis):
  *        E_z(z) = -[(Vb + Vd)/H - 2 Vd z / H^2]
  *  - Mobility: Caughey-Thomas form mu = mu0 / (1 + (E/Ec)^beta)^(1/beta)
@@ -93,7 +101,7 @@ typedef struct {
 } oc_event;
 
 enum { OC_OK = 0, OC_EINVAL = -1, OC_EMAXSTEPS = -5, OC_ENONFINITE = -6 };
-enum { OC_REPULSION = 1u, OC_DRIFT = 2u, OC_DIFFUSION = 4u, OC_ELECTRONS = 8u };
+enum { OC_REPULSION = 1u, OC_DRIFT = 2u, OC_DIFFUSION = 4u, OC_ELECTRONS = 8u, OC_SPHERICAL = 16u };
 
 /* SI exact values (e, k) and CODATA 2022 vacuum permittivity */
 static const double E_CHARGE = 1.602176634e-19; /* C */
@@ -256,6 +264,82 @@ void oc_field(const oc_params *p, int64_t n, const double *xyz, double *E)
     oc_field_q(p, n, xyz, NULL, E);
 }
 
+static int cmp_double(const void *a, const void *b)
+{
+    const double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Eq. 7 field of n holes at (x, y, z) on each other (E* [n]).  The centre
+ * is the mean position; Q_i, the number of holes strictly closer to it than
+ * hole i, is the lower-bound position of i's squared distance in the sorted
+ * list of all squared distances. */
+static void spherical_field(const oc_params *p, int64_t n, const double *x, const double *y,
+                            const double *z, double *Ex, double *Ey, double *Ez)
+{
+    if (n <= 0) return;
+    const double K = oc_coulomb_k(p);
+    const double s2 = p->softening_um * p->softening_um;
+    double cx = 0.0, cy = 0.0, cz = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        cx += x[i];
+        cy += y[i];
+        cz += z[i];
+    }
+    cx /= (double)n;
+    cy /= (double)n;
+    cz /= (double)n;
+    double *r2 = malloc(sizeof(double) * (size_t)n);
+    double *sorted = malloc(sizeof(double) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        const double dx = x[i] - cx, dy = y[i] - cy, dz = z[i] - cz;
+        r2[i] = dx * dx + dy * dy + dz * dz;
+        sorted[i] = r2[i];
+    }
+    qsort(sorted, (size_t)n, sizeof(double), cmp_double);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t lo = 0, hi = n; /* first entry not below r2[i] */
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (sorted[mid] < r2[i]) lo = mid + 1;
+            else hi = mid;
+        }
+        const int64_t Q = lo;
+        if (Q == 0) {
+            Ex[i] = Ey[i] = Ez[i] = 0.0;
+            continue;
+        }
+        const double w = r2[i] + s2;
+        const double f = K * (double)Q / (w * sqrt(w));
+        Ex[i] = f * (x[i] - cx);
+        Ey[i] = f * (y[i] - cy);
+        Ez[i] = f * (z[i] - cz);
+    }
+    free(r2);
+    free(sorted);
+}
+
+/* Eq. 7 field of n holes on each other ([n][3] in, [n][3] out). */
+void oc_field_spherical(const oc_params *p, int64_t n, const double *xyz, double *E)
+{
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    double *x = malloc(sizeof(double) * m), *y = malloc(sizeof(double) * m);
+    double *z = malloc(sizeof(double) * m), *ex = malloc(sizeof(double) * m);
+    double *ey = malloc(sizeof(double) * m), *ez = malloc(sizeof(double) * m);
+    for (int64_t i = 0; i < n; ++i) {
+        x[i] = xyz[3 * i];
+        y[i] = xyz[3 * i + 1];
+        z[i] = xyz[3 * i + 2];
+    }
+    spherical_field(p, n, x, y, z, ex, ey, ez);
+    for (int64_t i = 0; i < n; ++i) {
+        E[3 * i] = ex[i];
+        E[3 * i + 1] = ey[i];
+        E[3 * i + 2] = ez[i];
+    }
+    free(x); free(y); free(z); free(ex); free(ey); free(ez);
+}
+
 /* Repulsion field on selected carriers only: E[t] for carrier targets[t] of
  * the n carriers in xyz (each target costs O(n)). */
 void oc_field_targets(const oc_params *p, int64_t n, const double *xyz, int64_t n_t,
@@ -316,7 +400,8 @@ static int check_params(const oc_params *p)
         return OC_EINVAL;
     if (!(p->pair_energy_ev > 0.0) || p->mobility < 0 || p->mobility > 1) return OC_EINVAL;
     if ((p->physics & OC_DRIFT) && !(p->v_bias > p->v_dep && p->v_dep >= 0.0)) return OC_EINVAL;
-    if (p->physics & ~15u) return OC_EINVAL;
+    if (p->physics & ~31u) return OC_EINVAL;
+    if ((p->physics & OC_SPHERICAL) && (p->physics & OC_ELECTRONS)) return OC_EINVAL;
     for (int e = 0; e < 2; ++e) {
         double m[3];
         oc_mobility_params_of(p, e, m);
@@ -333,6 +418,7 @@ typedef struct {
     unsigned char *alive;
     int64_t *act; /* indices of the alive carriers, in carrier order */
     double *ax, *ay, *az, *aq;
+    double *sx, *sy, *sz; /* spherical-model field of the alive set */
 } oc_work;
 
 static void retire(const oc_params *p, oc_work *w, int32_t i, int64_t step, int32_t *pix,
@@ -394,6 +480,9 @@ static int run_event(const oc_params *p, const oc_event *ev, uint64_t eid, int p
     w.ay = malloc(nd * sizeof(double));
     w.az = malloc(nd * sizeof(double));
     w.aq = malloc(nd * sizeof(double));
+    w.sx = malloc(nd * sizeof(double));
+    w.sy = malloc(nd * sizeof(double));
+    w.sz = malloc(nd * sizeof(double));
     w.id = malloc(nd * sizeof(int32_t));
     w.alive = malloc(nd);
     w.act = malloc(nd * sizeof(int64_t));
@@ -451,13 +540,21 @@ static int run_event(const oc_params *p, const oc_event *ev, uint64_t eid, int p
         }
         *pairs_out += (uint64_t)na * (uint64_t)(na - 1);
         *hole_steps_out += (uint64_t)na;
+        const int spherical = (p->physics & OC_SPHERICAL) && (p->physics & OC_REPULSION);
+        if (spherical) spherical_field(p, na, w.ax, w.ay, w.az, w.sx, w.sy, w.sz);
 #pragma omp parallel for schedule(static) if (parallel_targets)
         for (int64_t a = 0; a < na; ++a) {
             const int64_t i = w.act[a];
             const int electron = i >= w.nh;
             const double sign = electron ? -1.0 : 1.0; /* velocity along q_i E */
             double Er[3] = {0.0, 0.0, 0.0};
-            if (p->physics & OC_REPULSION) repulsion_one(p, na, w.ax, w.ay, w.az, w.aq, a, K, Er);
+            if (spherical) {
+                Er[0] = w.sx[a];
+                Er[1] = w.sy[a];
+                Er[2] = w.sz[a];
+            } else if (p->physics & OC_REPULSION) {
+                repulsion_one(p, na, w.ax, w.ay, w.az, w.aq, a, K, Er);
+            }
             const double Ex = Er[0], Ey = Er[1], Ez = Er[2] + oc_drift_field(p, w.az[a]);
             const double Emag = sqrt(Ex * Ex + Ey * Ey + Ez * Ez);
             const double mu = oc_mobility_of(p, electron, Emag);
@@ -495,6 +592,7 @@ done:
     free(w.x); free(w.y); free(w.z);
     free(w.nx); free(w.ny); free(w.nz);
     free(w.ax); free(w.ay); free(w.az); free(w.aq);
+    free(w.sx); free(w.sy); free(w.sz);
     free(w.id); free(w.alive); free(w.act);
     return status;
 }

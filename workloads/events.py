@@ -50,6 +50,7 @@ class Sensor:
     mu0_e_override: float = math.nan  # electrons; NaN = model value at T
     ec_e_override: float = math.nan
     beta_e_override: float = math.nan
+    spherical: bool = False  # simplified spherical model of the repulsion field (Eq. 7)
     repulsion: bool = True
     drift: bool = True
     diffusion: bool = True
