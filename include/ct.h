@@ -83,8 +83,19 @@ typedef enum { CT_FP64 = 0, CT_FP32 = 1 } ct_precision;
 typedef enum { CT_MOB_JACOBONI = 0, CT_MOB_CONSTANT = 1 } ct_mobility;
 
 /* physics_flags bits: repulsion, drift and diffusion are the paper's method;
- * CT_ELECTRONS adds the electrons of every pair (two species) */
-enum { CT_REPULSION = 1u, CT_DRIFT = 2u, CT_DIFFUSION = 4u, CT_ELECTRONS = 8u };
+ * CT_ELECTRONS adds the electrons of every pair (two species).
+ * CT_SPHERICAL replaces the pairwise repulsion field (Eq. 4) by the
+ * simplified spherical model of Sec. 2.2, Eq. 7: the field at hole i is
+ *     K Q_i (r_i - c) / (|r_i - c|^2 + s^2)^(3/2),
+ * c being the mean position of the event's drifting holes at the step start
+ * and Q_i the number of them strictly closer to c than i (Q_i = 0: no
+ * field).  Holes only (with CT_ELECTRONS: CT_EINVAL).  It is evaluated in
+ * FP64 whatever the precision, one workgroup per event runs all of the
+ * event's steps of a ct_step call, and the launch configuration
+ * (ct_set_launch) has no effect.  The enclosed counts come from a counting
+ * sort over 8192 bins per event and step; a bin holding many holes at nearly
+ * the same distance costs time quadratic in its size. */
+enum { CT_REPULSION = 1u, CT_DRIFT = 2u, CT_DIFFUSION = 4u, CT_ELECTRONS = 8u, CT_SPHERICAL = 16u };
 
 /* options bits */
 enum {
@@ -111,7 +122,8 @@ typedef struct {
     double mu0_override;       /* holes: um^2/(V ns); NaN = model value */
     double ec_override;        /* holes: V/um; NaN = model value */
     double beta_override;      /* holes: NaN = model value */
-    uint32_t physics_flags;    /* CT_REPULSION | CT_DRIFT | CT_DIFFUSION [| CT_ELECTRONS] */
+    uint32_t physics_flags;    /* CT_REPULSION | CT_DRIFT | CT_DIFFUSION
+                                  [| CT_ELECTRONS or CT_SPHERICAL] */
     int32_t precision;         /* ct_precision */
     uint64_t seed;             /* Philox4x32-10 key = (low 32 bits, high 32 bits) */
     int64_t max_steps;         /* default step cap for ct_step (> 0) */
@@ -217,10 +229,11 @@ ct_status ct_step(ct_ctx *c, int64_t max_steps, int64_t *steps_done, int64_t *n_
 ct_status ct_collect(ct_ctx *c, int32_t *pixel_counts, double *xyz, int32_t *collect_step,
                      int64_t *event_steps, ct_run_stats *stats);
 
-/* Field of the other carriers (V/um, Eq. 4, each source with its sign) at
- * every carrier, as the next step would use it, computed by the same
- * kernels and precision as ct_step ([N_total][3], carrier order); drifting
- * carriers only, NaN for collected. */
+/* Field of the other carriers (V/um, Eq. 4, each source with its sign; with
+ * CT_SPHERICAL the field of Eq. 7) at every carrier, as the next step would
+ * use it, computed by the same kernels and precision as ct_step
+ * ([N_total][3], carrier order); drifting carriers only, NaN for
+ * collected. */
 ct_status ct_field(ct_ctx *c, double *field);
 
 /* Philox4x32-10 blocks and the Box-Muller normals the kernels derive from

@@ -31,7 +31,7 @@ CT_ABI_VERSION = 2
 CT_OK, CT_EINVAL, CT_ESTATE, CT_ENOMEM, CT_EDEVICE, CT_EMAXSTEPS, CT_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 CT_FP64, CT_FP32 = 0, 1
 CT_MOB_JACOBONI, CT_MOB_CONSTANT = 0, 1
-CT_REPULSION, CT_DRIFT, CT_DIFFUSION, CT_ELECTRONS = 1, 2, 4, 8
+CT_REPULSION, CT_DRIFT, CT_DIFFUSION, CT_ELECTRONS, CT_SPHERICAL = 1, 2, 4, 8, 16
 CT_OPT_TIMING = 1
 CT_OPT_AUTOTUNE = 4
 
@@ -138,7 +138,8 @@ def _dp(a):
 def make_params(sensor, precision: int = CT_FP64, stream=None, device: int = -1,
                 options: int = 0) -> ct_sensor_params:
     flags = (CT_REPULSION if sensor.repulsion else 0) | (CT_DRIFT if sensor.drift else 0) | \
-        (CT_DIFFUSION if sensor.diffusion else 0) | (CT_ELECTRONS if sensor.electrons else 0)
+        (CT_DIFFUSION if sensor.diffusion else 0) | (CT_ELECTRONS if sensor.electrons else 0) | \
+        (CT_SPHERICAL if sensor.spherical else 0)
     mob = {"jacoboni": CT_MOB_JACOBONI, "constant": CT_MOB_CONSTANT}[sensor.mobility]
     return ct_sensor_params(
         CT_ABI_VERSION, sensor.thickness_um, sensor.v_bias, sensor.v_dep, sensor.temperature_k,

@@ -96,7 +96,9 @@ ct_status check_params(const ct_sensor_params *p)
         return fail(CT_EINVAL, "unknown mobility model %d", p->mobility);
     if (p->precision != CT_FP64 && p->precision != CT_FP32)
         return fail(CT_EINVAL, "unknown precision %d", p->precision);
-    if (p->physics_flags & ~15u) return fail(CT_EINVAL, "unknown physics flag bits");
+    if (p->physics_flags & ~31u) return fail(CT_EINVAL, "unknown physics flag bits");
+    if ((p->physics_flags & CT_SPHERICAL) && (p->physics_flags & CT_ELECTRONS))
+        return fail(CT_EINVAL, "the spherical model (Eq. 7) simulates holes only");
     if ((p->physics_flags & CT_DRIFT) && !(p->v_bias > p->v_dep && p->v_dep >= 0.0))
         return fail(CT_EINVAL, "the linear drift field needs 0 <= v_dep < v_bias (Eq. 6)");
     if (p->max_steps <= 0) return fail(CT_EINVAL, "max_steps must be > 0");
@@ -155,13 +157,15 @@ double initial_sigma(const ct_event_desc &e)
 
 // Byte layout of one batch inside a single device buffer.
 struct Layout {
-    size_t off, n_act, n_hole, nh0, ev_step, ev_taken, call_steps, ref, pos, idx, nidx, rngid, out_xyz, out_cstep, pix,
-        pairs, hsteps, sigma, dep_off, deposits, x_off, xyz_in, start, total;
+    size_t off, n_act, n_hole, nh0, ev_step, ev_taken, call_steps, ref, pos, idx, nidx, rngid,
+        out_xyz, out_cstep, pix, pairs, hsteps, sigma, dep_off, deposits, x_off, xyz_in, start,
+        sph, total;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-Layout make_layout(int64_t B, int64_t N, int64_t n_dep, int64_t n_exp, int G1)
+// spherical: room for the keys of the spherical model (2 N doubles).
+Layout make_layout(int64_t B, int64_t N, int64_t n_dep, int64_t n_exp, int G1, bool spherical)
 {
     Layout L{};
     size_t o = 0;
@@ -193,6 +197,7 @@ Layout make_layout(int64_t B, int64_t N, int64_t n_dep, int64_t n_exp, int G1)
     L.x_off = take(sizeof(int32_t) * (B + 1));
     L.xyz_in = take(sizeof(double) * 3 * n_exp);
     L.start = take(sizeof(int64_t) * B);
+    L.sph = take(spherical ? sizeof(double) * 2 * N : 0);
     L.total = o;
     return L;
 }
@@ -277,7 +282,10 @@ struct QueueLayout {
     std::vector<int64_t> part_off_h;
 };
 
-QueueLayout make_queue_layout(const BatchShape &s, const ct::LaunchCfg &cfg, bool repulsion)
+// The spherical model runs without a queue: it keeps only the control block
+// (and minimal arrays).
+QueueLayout make_queue_layout(const BatchShape &s, const ct::LaunchCfg &cfg, bool repulsion,
+                              bool spherical)
 {
     QueueLayout Q{};
     const int64_t T = (int64_t)cfg.kt * cfg.bs;
@@ -286,10 +294,10 @@ QueueLayout make_queue_layout(const BatchShape &s, const ct::LaunchCfg &cfg, boo
     int64_t items = 0;
     for (int64_t b = 0; b < s.B; ++b) {
         const int64_t n0 = s.n[b];
-        const int64_t tiles = (n0 + T - 1) / T;
+        const int64_t tiles = spherical ? 0 : (n0 + T - 1) / T;
         // chunks of any later (smaller) count stay within this bound
         int64_t chunks = 1;
-        if (repulsion && n0 > 0)
+        if (repulsion && n0 > 0 && !spherical)
             chunks = std::min<int64_t>((n0 + cfg.chunk - 1) / cfg.chunk, ct::kMaxChunks);
         Q.tile_base_h[b + 1] = Q.tile_base_h[b] + (int32_t)tiles;
         Q.part_off_h[b + 1] = Q.part_off_h[b] + (chunks > 1 ? 3 * n0 * chunks : 0);
@@ -414,7 +422,8 @@ ct_status set_device(ct_ctx *c)
 ct_status prepare_queue(ct_ctx *c, const ct::LaunchCfg &cfg)
 {
     const bool repulsion = (c->p.physics_flags & CT_REPULSION) != 0;
-    QueueLayout Q = make_queue_layout(c->shape, cfg, repulsion);
+    const bool spherical = (c->p.physics_flags & CT_SPHERICAL) != 0;
+    QueueLayout Q = make_queue_layout(c->shape, cfg, repulsion, spherical);
     hipStream_t sm = c->stream;
     if (Q.total > c->qbuf_bytes) {
         if (c->qbuf) {
@@ -452,6 +461,10 @@ ct_status prepare_queue(ct_ctx *c, const ct::LaunchCfg &cfg)
         CT_HIP(hipStreamSynchronize(sm));  // host vectors go out of scope
     }
     c->dq = d;
+    if (spherical) {
+        c->grid = (int)c->shape.B;  // one workgroup per event
+        return CT_OK;
+    }
     const int occ = ct::run_occupancy(cfg, c->p.precision == CT_FP32);
     if (occ <= 0) return fail(CT_EDEVICE, "run kernel occupancy query failed");
     c->grid = occ * c->cu_count;
@@ -496,6 +509,30 @@ ct_status run_once(ct_ctx *c, const ct::LaunchCfg &cfg, int64_t max_steps, int f
     return CT_OK;
 }
 
+// One run of the spherical model: every event to completion or the step cap
+// (or, field_only, the field of its drifting holes), then the drifting-hole
+// count and steps taken.
+ct_status run_sph(ct_ctx *c, int64_t max_steps, int field_only, double *field_out, bool timing)
+{
+    hipStream_t sm = c->stream;
+    if (timing) CT_HIP(hipEventRecord(c->ev_a, sm));
+    CT_HIP(ct::launch_sph(c->dp, c->bt, at<double>(c->ws, c->L.sph), max_steps, field_only,
+                          field_out, sm));
+    if (timing) CT_HIP(hipEventRecord(c->ev_b, sm));
+    CT_HIP(ct::launch_summary(c->bt, c->dq.sc, sm));
+    CT_HIP(hipMemcpyAsync(c->h_sched, c->dq.sc, sizeof(ct::Sched), hipMemcpyDeviceToHost, sm));
+    CT_HIP(hipStreamSynchronize(sm));
+    if (timing) {
+        float ms = 0.0f;
+        CT_HIP(hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
+        c->field_ms += ms;
+        c->field_launches += 1;
+    }
+    return CT_OK;
+}
+
+bool spherical(const ct_ctx *c) { return (c->p.physics_flags & CT_SPHERICAL) != 0; }
+
 ct_status ensure_field_buf(ct_ctx *c, int64_t N)
 {
     if (c->field_buf_n >= (size_t)N) return CT_OK;
@@ -515,6 +552,7 @@ ct_status field_into_buf(ct_ctx *c, const ct::LaunchCfg &cfg, bool timing)
 {
     const int64_t N = c->shape.N;
     CT_HIP(ct::launch_fill_i32((int32_t *)c->field_buf, 6 * N, (int32_t)0xFFFFFFFF, c->stream));
+    if (spherical(c)) return run_sph(c, INT64_MAX, 1, c->field_buf, timing);
     return run_once(c, cfg, INT64_MAX, 1, c->field_buf, timing);
 }
 
@@ -610,7 +648,9 @@ size_t ct_workspace_bytes(const ct_sensor_params *p, const ct_event_desc *ev, in
     if (check_params(p) != CT_OK) return 0;
     BatchShape s;
     if (shape_of(*p, ev, n_events, s) != CT_OK) return 0;
-    return make_layout(s.B, s.N, s.n_dep, s.n_exp, p->grid_n * p->grid_n + 1).total;
+    return make_layout(s.B, s.N, s.n_dep, s.n_exp, p->grid_n * p->grid_n + 1,
+                       (p->physics_flags & CT_SPHERICAL) != 0)
+        .total;
 }
 
 ct_status ct_init_sensor(const ct_sensor_params *p, ct_ctx **out)
@@ -739,7 +779,7 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     }
     st = set_device(c);
     if (st != CT_OK) return st;
-    const Layout L = make_layout(s.B, s.N, s.n_dep, s.n_exp, G1);
+    const Layout L = make_layout(s.B, s.N, s.n_dep, s.n_exp, G1, (c->p.physics_flags & CT_SPHERICAL) != 0);
     c->seeded = false;
     st = ensure_workspace(c, L.total);
     if (st != CT_OK) return st;
@@ -820,7 +860,8 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     c->field_ms = 0.0;
     c->step_wall_ms = 0.0;
     c->seeded = true;
-    if ((c->p.options & CT_OPT_AUTOTUNE) && (c->p.physics_flags & CT_REPULSION) && s.N > 0) {
+    if ((c->p.options & CT_OPT_AUTOTUNE) && (c->p.physics_flags & CT_REPULSION) && s.N > 0 &&
+        !spherical(c)) {
         st = autotune(c);
         if (st != CT_OK) return st;
     }
@@ -840,12 +881,17 @@ ct_status ct_step(ct_ctx *c, int64_t max_steps, int64_t *steps_done, int64_t *n_
     int64_t done = 0;
     if (c->n_active > 0) {
         CT_HIP(ct::launch_fill_i32((int32_t *)c->bt.call_steps, 2 * c->shape.B, 0, c->stream));
-        // one run takes every event to completion or to the step cap, unless
-        // the work queue filled up and some events were parked
-        for (;;) {
-            st = run_once(c, c->cfg, max_steps, 0, nullptr, timing);
+        if (spherical(c)) {
+            st = run_sph(c, max_steps, 0, nullptr, timing);
             if (st != CT_OK) return st;
-            if (!c->h_sched->exhausted.v) break;
+        } else {
+            // one run takes every event to completion or to the step cap,
+            // unless the work queue filled up and some events were parked
+            for (;;) {
+                st = run_once(c, c->cfg, max_steps, 0, nullptr, timing);
+                if (st != CT_OK) return st;
+                if (!c->h_sched->exhausted.v) break;
+            }
         }
         c->n_active = c->h_sched->active;
         done = c->h_sched->max_steps;
@@ -902,9 +948,9 @@ ct_status ct_collect(ct_ctx *c, int32_t *pixel_counts, double *xyz, int32_t *col
         r.field_launches = c->field_launches;
         r.field_kernel_ms = c->field_ms;
         r.step_wall_ms = c->step_wall_ms;
-        r.targets_per_thread = c->cfg.kt;
-        r.block_size = c->cfg.bs;
-        r.chunk_len = c->cfg.chunk;
+        r.targets_per_thread = spherical(c) ? 1 : c->cfg.kt;
+        r.block_size = spherical(c) ? ct::sph_block() : c->cfg.bs;
+        r.chunk_len = spherical(c) ? 0 : c->cfg.chunk;
         r.workgroups = c->grid;
         *stats = r;
     }

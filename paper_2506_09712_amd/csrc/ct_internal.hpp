@@ -21,7 +21,7 @@ struct DevParams {
     float s2f;
     int32_t grid_n;
     int32_t mobility;  // 0 Caughey-Thomas (Jacoboni-Canali), 1 constant
-    uint32_t flags;    // repulsion 1, drift 2, diffusion 4, electrons 8
+    uint32_t flags;    // repulsion 1, drift 2, diffusion 4, electrons 8, spherical model 16
     uint32_t key0, key1;
 };
 
@@ -125,6 +125,11 @@ hipError_t launch_run(const DevParams &dp, const DevBatch &bt, const DevQueue &d
                       const LaunchCfg &cfg, int fp32, int grid, int64_t max_steps, int field_only,
                       double *field_out, hipStream_t s);
 hipError_t launch_summary(const DevBatch &bt, Sched *sc, hipStream_t s);
+// Simplified spherical model (Eq. 7), one workgroup per event; scratch holds
+// 2 * n_total doubles.
+hipError_t launch_sph(const DevParams &dp, const DevBatch &bt, double *scratch, int64_t max_steps,
+                      int field_only, double *field_out, hipStream_t s);
+int sph_block();
 int run_occupancy(const LaunchCfg &cfg, int fp32);
 bool launch_supported(int kt, int bs);
 hipError_t launch_scatter_alive(const DevBatch &bt, int n_max, hipStream_t s);

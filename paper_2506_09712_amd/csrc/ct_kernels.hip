@@ -308,13 +308,16 @@ __device__ __forceinline__ void pair_f64(const D4 &s, double s2, const double (&
 // first nh of the n slots; electrons: z < H) are packed to the front of the
 // event's slots in carrier order by the NT threads of one workgroup, from the
 // post-step arrays (nx, ny, nz, nidx) into the current ones (cx, cy, cz,
-// idx); surviving holes therefore stay ahead of surviving electrons.  Windows of kCompactChunks chunks of NT slots:
+// idx); surviving holes therefore stay ahead of surviving electrons.  Windows
+// of kCompactChunks chunks of NT slots:
 // every z of a window is loaded at once, each wave ranks its survivors with
 // a 64-bit ballot and mbcnt per chunk, one barrier publishes the wave totals,
 // and the survivors are copied with independent loads and stores, so about
 // two memory latencies are exposed per window.  n is the event's count
 // before the step.  Thread 0 stores the new counts (all, holes) and the
-// centroid (summed in a fixed order) and, for a step, counts it.  Returns the
+// centroid (summed in a fixed order; within a wave, neighbouring lanes
+// first, so that partners at adjacent slots of a point-symmetric cloud cancel
+// exactly) and, for a step, counts it.  Returns the
 // survivors (in every thread) and, in thread 0, the surviving holes; ends
 // with a barrier.
 constexpr int kCompactChunks = 8;
@@ -379,11 +382,11 @@ __device__ int compact_event(const DevBatch &bt, int b, int n, int nh, double H,
         kept = before;
         __syncthreads();  // wave totals of this window are read before the next overwrites them
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        sx += __shfl_down(sx, o);
-        sy += __shfl_down(sy, o);
-        sz += __shfl_down(sz, o);
-        my_holes += __shfl_down(my_holes, o);
+    for (int o = 1; o < 64; o <<= 1) {
+        sx += __shfl_xor(sx, o);
+        sy += __shfl_xor(sy, o);
+        sz += __shfl_xor(sz, o);
+        my_holes += __shfl_xor(my_holes, o);
     }
     if (lane == 0) {
         wsum[0 * W + wave] = sx;
@@ -829,6 +832,167 @@ __global__ __launch_bounds__(1024) void k_init(DevBatch bt, DevQueue dq, int T, 
     }
 }
 
+// ------------------------------------------------ simplified spherical model
+
+// Eq. 7: the field at hole i is K Q_i (r_i - c) / (|r_i - c|^2 + s^2)^(3/2),
+// with c the mean position of the event's drifting holes and Q_i the number
+// of them strictly closer to c than i.  One workgroup takes one event through
+// all its steps of a call (no other workgroup touches the event).  Q_i comes
+// from a counting sort of the squared distances (keys): kSphBins LDS
+// counters over [0, largest key], a bin being a monotone function of the key,
+// so Q_i = (keys in lower bins) + (keys of its own bin below its own).  The
+// update and the compaction (which also yields the next centre) are those of
+// the brute-force path.
+constexpr int kSphBlock = 512;
+constexpr int kSphBins = 8192;
+
+// Squared distance from the centre, summed left to right without fused
+// multiply-adds: enclosed counts are decided by comparing these values.
+__device__ __forceinline__ double sq_dist(double dx, double dy, double dz)
+{
+#pragma clang fp contract(off)
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// Bin of a key in [0, largest key]: non-decreasing in the key, always in
+// [0, kSphBins) (a key that is not finite goes to the last bin).
+__device__ __forceinline__ int sph_bin(double key, double scale)
+{
+    const double v = key * scale;  // in [0, kSphBins (1 + eps)] for finite keys
+    return v < (double)(kSphBins - 1) ? (int)v : kSphBins - 1;
+}
+
+// Largest v over the workgroup, in every thread.  Contains a workgroup
+// barrier, so the workgroup's earlier LDS and memory writes are visible to
+// all of it afterwards.
+template <int BS>
+__device__ double block_max(double v, double *red)
+{
+    constexpr int W = BS / 64;
+    for (int o = 1; o < 64; o <<= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = red[0];
+#pragma unroll
+    for (int q = 1; q < W; ++q) m = fmax(m, red[q]);
+    return m;
+}
+
+// Inclusive prefix sum of the kSphBins LDS counters h, in place; each thread
+// owns kSphBins / BS consecutive counters.  Ends with a barrier.
+template <int BS>
+__device__ void scan_bins(int *h, int *wtot)
+{
+    constexpr int R = kSphBins / BS;
+    constexpr int W = BS / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int v[R];
+    int run = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        run += h[tid * R + r];
+        v[r] = run;
+    }
+    int inc = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    int before = inc - run;
+#pragma unroll
+    for (int q = 0; q < W; ++q) before += q < wave ? wtot[q] : 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) h[tid * R + r] = before + v[r];
+    __syncthreads();
+}
+
+struct SphArgs {
+    double *key;        // [N] by slot: squared distance of the hole from its event's centre
+    double *sorted;     // [N] by slot: the event's keys grouped by bin
+    int field_only;     // 1: write the field of every drifting hole, no update
+    int64_t max_steps;  // steps per event in this call
+    double *field_out;  // [N][3] by carrier (field_only)
+};
+
+__global__ __launch_bounds__(kSphBlock) void k_sph(DevParams dp, DevBatch bt, SphArgs sa)
+{
+    constexpr int BS = kSphBlock, W = BS / 64;
+    static_assert(kSphBins % BS == 0, "bins per thread");
+    __shared__ int hist[kSphBins];
+    __shared__ int wtot[W];
+    __shared__ double red[W];
+    __shared__ int s_wcount[kCompactChunks * W];
+    __shared__ double s_wsum[3 * W];
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int base = bt.off[b];
+    const uint32_t eid = (uint32_t)(bt.first_event_id + b);
+    const bool repulsion = (dp.flags & 1u) != 0;
+    int n = bt.n_act[b];  // drifting holes (the model has no electrons)
+    int64_t step = bt.ev_step[b];
+    int64_t taken = bt.call_steps[b];
+    while (n > 0 && (sa.field_only || taken < sa.max_steps)) {
+        const double cx = bt.ref[4 * b + 0], cy = bt.ref[4 * b + 1], cz = bt.ref[4 * b + 2];
+        double scale = 0.0;
+        if (repulsion) {
+            double mx = 0.0;
+            for (int s = tid; s < n; s += BS) {
+                const double k = sq_dist(bt.cx[base + s] - cx, bt.cy[base + s] - cy,
+                                         bt.cz[base + s] - cz);
+                sa.key[base + s] = k;
+                mx = fmax(mx, k);
+            }
+            for (int i = tid; i < kSphBins; i += BS) hist[i] = 0;
+            mx = block_max<BS>(mx, red);
+            scale = mx > 1e-300 ? (double)kSphBins / mx : 0.0;
+            for (int s = tid; s < n; s += BS) atomicAdd(&hist[sph_bin(sa.key[base + s], scale)], 1);
+            __syncthreads();
+            scan_bins<BS>(hist, wtot);  // hist[q] = end of bin q
+            for (int s = tid; s < n; s += BS) {
+                const double k = sa.key[base + s];
+                const int pos = atomicSub(&hist[sph_bin(k, scale)], 1) - 1;
+                sa.sorted[base + pos] = k;
+            }
+            __syncthreads();  // hist[q] = start of bin q; the grouped keys are written
+        }
+        for (int s = tid; s < n; s += BS) {
+            double ex = 0.0, ey = 0.0, ez = 0.0;
+            if (repulsion) {
+                const double k = sa.key[base + s];
+                const int q = sph_bin(k, scale);
+                const int lo = hist[q];
+                const int hi = q + 1 < kSphBins ? hist[q + 1] : n;
+                int inside = lo;
+                for (int j = lo; j < hi; ++j) inside += sa.sorted[base + j] < k ? 1 : 0;
+                if (inside > 0) {
+                    const double w = k + dp.s2;
+                    const double f = dp.K * (double)inside / (w * sqrt(w));
+                    ex = f * (bt.cx[base + s] - cx);
+                    ey = f * (bt.cy[base + s] - cy);
+                    ez = f * (bt.cz[base + s] - cz);
+                }
+            }
+            if (sa.field_only) {
+                const int64_t carrier = bt.off[b] + bt.idx[base + s];
+                sa.field_out[3 * carrier + 0] = ex;
+                sa.field_out[3 * carrier + 1] = ey;
+                sa.field_out[3 * carrier + 2] = ez;
+            } else {
+                advance(dp, bt, b, base + s, ex, ey, ez, step, eid);
+            }
+        }
+        if (sa.field_only) break;
+        __syncthreads();  // every update is written before the compaction reads it
+        int holes_kept = 0;
+        n = compact_event<BS>(bt, b, n, n, dp.H, 1, s_wcount, s_wsum, holes_kept);
+        ++step;
+        ++taken;
+    }
+}
+
 // Drifting holes and the most steps any event took in this call.
 __global__ __launch_bounds__(1024) void k_summary(DevBatch bt, Sched *sc)
 {
@@ -1034,6 +1198,19 @@ hipError_t launch_run(const DevParams &dp, const DevBatch &bt, const DevQueue &d
 #undef CT_RUN_CASE
     return hipErrorInvalidValue;
 }
+
+// Simplified spherical model: every event with drifting holes to completion
+// or max_steps (or, field_only, its field), one workgroup per event.
+hipError_t launch_sph(const DevParams &dp, const DevBatch &bt, double *scratch, int64_t max_steps,
+                      int field_only, double *field_out, hipStream_t s)
+{
+    if (bt.n_events <= 0) return hipSuccess;
+    SphArgs sa{scratch, scratch + bt.n_total, field_only, max_steps, field_out};
+    hipLaunchKernelGGL(k_sph, dim3(bt.n_events), dim3(kSphBlock), 0, s, dp, bt, sa);
+    return hipGetLastError();
+}
+
+int sph_block() { return kSphBlock; }
 
 hipError_t launch_summary(const DevBatch &bt, Sched *sc, hipStream_t s)
 {
