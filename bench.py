@@ -9,6 +9,11 @@ Printed as one JSON line: pair-interactions/s of the FP32-batched path
 (value), events/s, the FP64-plain comparison (one event at a time, FP64
 field), the roofline of the repulsion-step kernel (timed with HIP events on
 the library's stream) and the FP64 CPU oracle timed on a bounded sample.
+
+--model spherical measures the simplified spherical model (Sec. 2.2, Eq. 7)
+on the same workload instead: events/s (value) and hole updates/s, the
+roofline of its kernel against HBM bandwidth, and the oracle's spherical
+model on a bounded sample.
 """
 from __future__ import annotations
 
@@ -24,7 +29,9 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 METRIC = "pair-interactions/s + events/s, FP32-batched vs FP64-plain at ≤1e-3 pixel-fraction err"
+METRIC_SPHERICAL = "events/s + hole-updates/s, simplified spherical model (Eq. 7), FP64"
 FP32_VECTOR_PEAK = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 64 lanes x 2 x 2 x 2.4 GHz)
+HBM_PEAK = 8.0e12             # MI355X HBM3E bytes/s
 FLOP_PER_PAIR = 20            # N-body convention for one softened pair interaction
 
 
@@ -34,6 +41,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batch_8kev")
+    ap.add_argument("--model", choices=("pairs", "spherical"), default="pairs",
+                    help="pairs: the brute-force field (Eq. 4); spherical: Eq. 7")
     ap.add_argument("--events", type=int, default=0, help="override the number of events")
     ap.add_argument("--plain-events", type=int, default=32,
                     help="events of the FP64-plain comparison (rate extrapolated)")
@@ -54,27 +63,43 @@ def parse():
 # the new FP64 position (24 B) written.  Sources are re-reads of the same
 # event's positions, served from cache.
 ALG_BYTES_PER_HOLE_STEP = 56
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_run_f32_batch_8kev_traffic.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2506_09712_amd", "csrc", "ct_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2506_09712_amd", "csrc")
+# the sources each kernel is built from, and its committed counter summary
+KERNEL_SOURCES = {
+    "pairs": ("ct_kernels.hip", "ct_device.hpp", "ct_internal.hpp"),
+    "spherical": ("ct_sph.hip", "ct_device.hpp", "ct_internal.hpp"),
+}
+TRAFFIC_PROFILES = {
+    "pairs": os.path.join(ROOT, "profiles", "k_run_f32_batch_8kev_traffic.md"),
+    "spherical": os.path.join(ROOT, "profiles", "k_sph_batch_8kev_traffic.md"),
+}
 
 
-def measured_traffic(hole_steps_per_launch):
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
-    summary (bytes per hole update), or None when the kernel source has
-    changed since the counters were taken."""
+def sources_digest(model):
+    """SHA-256 of the kernel's source files, concatenated in a fixed order."""
     import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[model]:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(model, hole_steps_per_launch):
+    """HBM bytes per kernel launch from the committed rocprofv3 counter
+    summary (bytes per hole update), or None when the kernel's sources have
+    changed since the counters were taken."""
+    path = TRAFFIC_PROFILES[model]
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(path).read()
     except OSError:
         return None, "no counter summary"
     vals = dict(line.split(":", 1) for line in text.splitlines()
-                if line.startswith(("bytes_per_hole_step:", "kernel_source_sha256:")))
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if vals.get("kernel_source_sha256", "").strip() != sha:
+                if line.startswith(("bytes_per_hole_step:", "kernel_sources_sha256:")))
+    if vals.get("kernel_sources_sha256", "").strip() != sources_digest(model):
         return None, "kernel changed since the counters were taken"
     per = float(vals["bytes_per_hole_step"])
     return per * hole_steps_per_launch, ("FETCH_SIZE and WRITE_SIZE per hole update, scaled by a "
-                                         "1 GiB copy; " + os.path.basename(TRAFFIC_PROFILE))
+                                         "1 GiB copy; " + os.path.basename(path))
 
 
 def simulate(ct, sim, batch):
@@ -118,6 +143,8 @@ def main():
               flush=True)
         del src, dst
 
+    if a.model == "spherical":
+        return spherical(a, ct, torch, sensor, batch, n_holes)
     tune = ct.CT_OPT_AUTOTUNE if (a.autotune and not launch) else 0
 
     def timed_runs(label):
@@ -146,7 +173,7 @@ def main():
     pairs, wall, kern_ms, launches, st, hsteps = timed_runs("fp32-batched")
     value = pairs / wall
     events_per_s = batch.n_events * a.steps / wall
-    traffic, traffic_note = measured_traffic(hsteps / max(launches, 1))
+    traffic, traffic_note = measured_traffic("pairs", hsteps / max(launches, 1))
     achieved = FLOP_PER_PAIR * pairs / (kern_ms * 1e-3) if kern_ms > 0 else None
     print(f"bench: step kernel {kern_ms / max(launches, 1):.3f} ms avg over {launches} launches, "
           f"{achieved / 1e12 if achieved else 0:.1f} TFLOP/s", file=sys.stderr, flush=True)
@@ -225,6 +252,74 @@ def main():
                                          f"to completion alone ({cpairs:.3e} pairs, {cwall:.1f} s)",
                                "events_per_s": k / cwall}
         print(f"bench: oracle {cpairs / cwall:.3e} pairs/s on {oracle.threads()} threads",
+              file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+def spherical(a, ct, torch, sensor, batch, n_holes):
+    """The simplified spherical model on the same workload: one k_sph launch
+    per run (one workgroup per event), FP64."""
+    if sensor.electrons:
+        raise SystemExit("the spherical model simulates holes only")
+    sensor = sensor.replace(spherical=True)
+    sim = ct.Simulator(sensor, ct.CT_FP64, device=0, options=ct.CT_OPT_TIMING)
+    for _ in range(a.warmup):
+        simulate(ct, sim, batch)
+    torch.cuda.synchronize()
+    kern_ms, launches, hsteps = 0.0, 0, 0
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        r = simulate(ct, sim, batch)
+        hsteps += r["hole_steps"]
+        kern_ms += r["stats"].field_kernel_ms
+        launches += r["stats"].field_launches
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = r["stats"]
+    sim.close()
+    events_per_s = batch.n_events * a.steps / wall
+    per_launch = hsteps / max(launches, 1)
+    achieved = ALG_BYTES_PER_HOLE_STEP * hsteps / (kern_ms * 1e-3) if kern_ms > 0 else None
+    traffic, traffic_note = measured_traffic("spherical", per_launch)
+    print(f"bench: spherical: {events_per_s:.1f} events/s, {hsteps / wall:.3e} hole updates/s; "
+          f"k_sph {kern_ms / max(launches, 1):.3f} ms avg over {launches} launches",
+          file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC_SPHERICAL, "value": events_per_s, "unit": "events/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * wall / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {batch.n_events} events, {n_holes} holes, "
+                               f"{sensor.thickness_um:g} um Si at {sensor.v_bias:g} V, "
+                               f"dt {sensor.dt_ns:g} ns; simplified spherical model (Eq. 7), FP64; "
+                               f"one workgroup per event for all of its steps",
+                   "events": batch.n_events, "holes": n_holes,
+                   "launch": {"block": st.block_size, "workgroups": st.workgroups}},
+        "hole_updates_per_s": hsteps / wall,
+        "hole_steps_per_run": hsteps // a.steps,
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9 if achieved else None,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK if achieved else None,
+                     "traffic": traffic, "traffic_note": traffic_note,
+                     "algorithmic_bytes_per_launch": ALG_BYTES_PER_HOLE_STEP * per_launch,
+                     "hole_steps_per_launch": per_launch, "kernel": "k_sph",
+                     "avg_launch_ms": kern_ms / max(launches, 1), "launches": launches},
+    }
+    if not a.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        ch, t2, k = 0, time.perf_counter(), 0
+        while k < batch.n_events and (time.perf_counter() - t2) < a.cpu_seconds:
+            ch += oracle.run(sensor, batch.event(k))["hole_steps"]
+            k += 1
+        cwall = time.perf_counter() - t2
+        out["cpu_baseline"] = {"value": k / cwall, "unit": "events/s", "cores": oracle.threads(),
+                               "kind": "oracle",
+                               "sample": f"events 0..{k - 1} of {a.workload}, spherical model, each "
+                                         f"simulated to completion alone ({ch:.3e} hole updates, "
+                                         f"{cwall:.1f} s)",
+                               "hole_updates_per_s": ch / cwall}
+        print(f"bench: oracle {k / cwall:.2f} events/s on {oracle.threads()} threads",
               file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 

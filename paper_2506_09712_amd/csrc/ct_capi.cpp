@@ -129,8 +129,10 @@ ct::DevParams make_dev_params(const ct_sensor_params &p)
     d.s2f = (float)d.s2;
     hole_mobility_params(p, d.mu0, d.ec, d.beta);
     d.inv_beta = 1.0 / d.beta;
+    d.inv_ec = 1.0 / d.ec;
     electron_mobility_params(p, d.mu0_e, d.ec_e, d.beta_e);
     d.inv_beta_e = 1.0 / d.beta_e;
+    d.inv_ec_e = 1.0 / d.ec_e;
     d.pitch = p.pitch_um;
     d.half_width = 0.5 * p.grid_n * p.pitch_um;
     d.grid_n = p.grid_n;

@@ -15,8 +15,8 @@ struct DevParams {
     double K;          // e / (4 pi eps0 eps_r) (V um)
     double kT;         // k T / e (V)
     double s2;         // softening^2 (um^2), never below a tiny floor
-    double mu0, ec, beta, inv_beta;           // holes
-    double mu0_e, ec_e, beta_e, inv_beta_e;   // electrons
+    double mu0, ec, beta, inv_beta, inv_ec;           // holes
+    double mu0_e, ec_e, beta_e, inv_beta_e, inv_ec_e; // electrons
     double pitch, half_width;  // pixel pitch, grid_n * pitch / 2
     float s2f;
     int32_t grid_n;
