@@ -33,11 +33,11 @@ __device__ __forceinline__ Ctr philox10(Ctr c, uint32_t k0, uint32_t k1)
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        // one 32 x 32 -> 64-bit product gives both halves
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c.c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.c2;
-        c = Ctr{(uint32_t)(p1 >> 32) ^ c.c1 ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.c3 ^ k1,
-                (uint32_t)p0};
+        // low and high halves as two independent products (a single 64-bit
+        // product measured slower: it lengthens the dependent chain)
+        const uint32_t lo0 = 0xD2511F53u * c.c0, hi0 = __umulhi(0xD2511F53u, c.c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c.c2, hi1 = __umulhi(0xCD9E8D57u, c.c2);
+        c = Ctr{hi1 ^ c.c1 ^ k0, lo1, hi0 ^ c.c3 ^ k1, lo0};
     }
     return c;
 }
