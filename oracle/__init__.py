@@ -68,6 +68,8 @@ def lib():
         dp, ip, up = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_uint32)
         L.oc_philox4x32_10.argtypes = [up, up, up]
         L.oc_normals3.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, dp]
+        L.oc_philox_many.argtypes = [C.c_uint64, C.c_int64, up, up]
+        L.oc_normals_many.argtypes = [C.c_uint64, C.c_int64, up, dp]
         L.oc_coulomb_k.argtypes = [C.POINTER(OcParams)]
         L.oc_coulomb_k.restype = C.c_double
         L.oc_thermal_voltage.argtypes = [C.POINTER(OcParams)]
@@ -139,6 +141,24 @@ def normals3(seed: int, c0: int, c1: int, c2: int, c3: int) -> np.ndarray:
     o = (C.c_double * 3)()
     lib().oc_normals3(seed, c0, c1, c2, c3, o)
     return np.array(list(o))
+
+
+def philox_many(seed: int, ctr: np.ndarray) -> np.ndarray:
+    """Philox4x32-10 blocks [n, 4] for counters [n, 4] under a 64-bit seed."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    out = np.empty_like(ctr)
+    lib().oc_philox_many(int(seed), ctr.shape[0], ctr.ctypes.data_as(C.POINTER(C.c_uint32)),
+                         out.ctypes.data_as(C.POINTER(C.c_uint32)))
+    return out
+
+
+def normals_many(seed: int, ctr: np.ndarray) -> np.ndarray:
+    """Box-Muller normals [n, 3] for counters [n, 4]."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    out = np.empty((ctr.shape[0], 3))
+    lib().oc_normals_many(int(seed), ctr.shape[0], ctr.ctypes.data_as(C.POINTER(C.c_uint32)),
+                          _dp(out))
+    return out
 
 
 def coulomb_k(sensor) -> float:

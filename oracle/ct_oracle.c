@@ -159,6 +159,20 @@ void oc_normals3(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t 
     n[2] = rb * cos(2.0 * PI * u3);
 }
 
+/* Philox blocks for n counters ([n][4] in, [n][4] out) under a 64-bit seed. */
+void oc_philox_many(uint64_t seed, int64_t n, const uint32_t *ctr, uint32_t *out)
+{
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t i = 0; i < n; ++i) oc_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
+/* Box-Muller normals for n counters ([n][4] in, [n][3] out). */
+void oc_normals_many(uint64_t seed, int64_t n, const uint32_t *ctr, double *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        oc_normals3(seed, ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], out + 3 * i);
+}
+
 /* ------------------------------------------------------------- physics */
 
 /* e / (4 pi eps0 eps_r) in V um: field of one elementary charge is K / r^2. */
