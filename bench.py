@@ -14,6 +14,11 @@ the library's stream) and the FP64 CPU oracle timed on a bounded sample.
 on the same workload instead: events/s (value) and hole updates/s, the
 roofline of its kernel against HBM bandwidth, and the oracle's spherical
 model on a bounded sample.
+
+--model generator measures the parameterised event generation (Sec. 4.2) on
+its own workload (one million 25 keV events): events/s (value) and carriers
+placed per second, the roofline of its kernel against the VALU issue rate,
+and the oracle's generator on a bounded sample.
 """
 from __future__ import annotations
 
@@ -30,6 +35,16 @@ import numpy as np  # noqa: E402
 
 METRIC = "pair-interactions/s + events/s, FP32-batched vs FP64-plain at ≤1e-3 pixel-fraction err"
 METRIC_SPHERICAL = "events/s + hole-updates/s, simplified spherical model (Eq. 7), FP64"
+METRIC_GENERATOR = "events/s + carriers/s, parameterised event generation (Sec. 4.2)"
+# VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one vector operation
+# per lane per clock
+VALU_OP_PEAK = 256 * 64 * 2.4e9
+# Algorithmic vector operations per generated carrier: half a Philox4x32-10
+# block (10 rounds of 2 low and 2 high 32-bit products and 4 XORs per two
+# carriers: 40), 2 uniform conversions (4), two searches over the 6 pixel
+# edges of a 5-pixel row (24 compares and adds), the pixel index and the
+# histogram update (4)
+OPS_PER_CARRIER = 72
 FP32_VECTOR_PEAK = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 64 lanes x 2 x 2 x 2.4 GHz)
 HBM_PEAK = 8.0e12             # MI355X HBM3E bytes/s
 FLOP_PER_PAIR = 20            # N-body convention for one softened pair interaction
@@ -41,8 +56,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batch_8kev")
-    ap.add_argument("--model", choices=("pairs", "spherical"), default="pairs",
-                    help="pairs: the brute-force field (Eq. 4); spherical: Eq. 7")
+    ap.add_argument("--model", choices=("pairs", "spherical", "generator"), default="pairs",
+                    help="pairs: the brute-force field (Eq. 4); spherical: Eq. 7; generator: "
+                         "the parameterised events of Sec. 4.2")
     ap.add_argument("--events", type=int, default=0, help="override the number of events")
     ap.add_argument("--plain-events", type=int, default=32,
                     help="events of the FP64-plain comparison (rate extrapolated)")
@@ -68,10 +84,12 @@ CSRC = os.path.join(ROOT, "paper_2506_09712_amd", "csrc")
 KERNEL_SOURCES = {
     "pairs": ("ct_kernels.hip", "ct_device.hpp", "ct_internal.hpp"),
     "spherical": ("ct_sph.hip", "ct_device.hpp", "ct_internal.hpp"),
+    "generator": ("ct_gen.hip", "ct_device.hpp", "ct_internal.hpp"),
 }
 TRAFFIC_PROFILES = {
     "pairs": os.path.join(ROOT, "profiles", "k_run_f32_batch_8kev_traffic.md"),
     "spherical": os.path.join(ROOT, "profiles", "k_sph_batch_8kev_traffic.md"),
+    "generator": os.path.join(ROOT, "profiles", "k_gen_generator_25kev_traffic.md"),
 }
 
 
@@ -84,22 +102,23 @@ def sources_digest(model):
     return h.hexdigest()
 
 
-def measured_traffic(model, hole_steps_per_launch):
+def measured_traffic(model, units_per_launch):
     """HBM bytes per kernel launch from the committed rocprofv3 counter
-    summary (bytes per hole update), or None when the kernel's sources have
-    changed since the counters were taken."""
+    summary (bytes per hole update; per event for the generator), or None when
+    the kernel's sources have changed since the counters were taken."""
     path = TRAFFIC_PROFILES[model]
     try:
         text = open(path).read()
     except OSError:
         return None, "no counter summary"
+    unit = "bytes_per_event" if model == "generator" else "bytes_per_hole_step"
     vals = dict(line.split(":", 1) for line in text.splitlines()
-                if line.startswith(("bytes_per_hole_step:", "kernel_sources_sha256:")))
+                if line.startswith((unit + ":", "kernel_sources_sha256:")))
     if vals.get("kernel_sources_sha256", "").strip() != sources_digest(model):
         return None, "kernel changed since the counters were taken"
-    per = float(vals["bytes_per_hole_step"])
-    return per * hole_steps_per_launch, ("FETCH_SIZE and WRITE_SIZE per hole update, scaled by a "
-                                         "1 GiB copy; " + os.path.basename(path))
+    per = float(vals[unit])
+    return per * units_per_launch, ("FETCH_SIZE and WRITE_SIZE per unit of work, scaled by a "
+                                     "1 GiB copy; " + os.path.basename(path))
 
 
 def simulate(ct, sim, batch):
@@ -123,6 +142,8 @@ def main():
     from workloads import make_workload
 
     kw = {"n_events": a.events} if a.events else {}
+    if a.model == "generator":
+        return generator(a, ct, torch, kw)
     sensor, batch = make_workload(a.workload, **kw)
     launch = tuple(int(v) for v in a.launch.split(",")) if a.launch else None
     dev = torch.device("cuda:0")
@@ -253,6 +274,79 @@ def main():
                                "events_per_s": k / cwall}
         print(f"bench: oracle {cpairs / cwall:.3e} pairs/s on {oracle.threads()} threads",
               file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+def generator(a, ct, torch, kw):
+    """One ct_generate launch per step into device buffers allocated once
+    (inputs are the parameters only; outputs stay in HBM)."""
+    from workloads import generator_25kev
+    sensor, gen, n = generator_25kev(**kw)
+    G = sensor.grid_n
+    dev = torch.device("cuda:0")
+    print(f"bench: generator_25kev {n} events, {G}x{G} pixels; warmup {a.warmup}, steps {a.steps}",
+          file=sys.stderr, flush=True)
+    if a.copy_calibration_mb:
+        src = torch.ones(a.copy_calibration_mb << 20, dtype=torch.uint8, device=dev)
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        print(f"bench: calibration copy of {a.copy_calibration_mb} MiB done", file=sys.stderr,
+              flush=True)
+        del src
+    energy = torch.empty((n, G * G), dtype=torch.float64, device=dev)
+    counts = torch.empty((n, G * G + 1), dtype=torch.int32, device=dev)
+    info = torch.empty((n, 5), dtype=torch.float64, device=dev)
+    ctx = ct.ct_init_sensor(ct.make_params(sensor, ct.CT_FP64,
+                                           stream=torch.cuda.current_stream(0).cuda_stream, device=0))
+    ptrs = (energy.data_ptr(), counts.data_ptr(), info.data_ptr())
+    for w in range(a.warmup):
+        ct.ct_generate(ctx, gen, n, w * n, *ptrs)
+    torch.cuda.synchronize()
+    kern_ms, carriers = 0.0, 0
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        kern_ms += ct.ct_generate(ctx, gen, n, (a.warmup + k) * n, *ptrs, timed=True)
+        carriers += int(info[:, 2].sum().item())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ct.ct_destroy(ctx)
+    events_per_s = n * a.steps / wall
+    achieved = OPS_PER_CARRIER * carriers / (kern_ms * 1e-3)
+    traffic, traffic_note = measured_traffic("generator", n)
+    print(f"bench: generator: {events_per_s:.4g} events/s, {carriers / wall:.4g} carriers/s; k_gen "
+          f"{kern_ms / a.steps:.3f} ms avg over {a.steps} launches", file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC_GENERATOR, "value": events_per_s, "unit": "events/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * wall / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"generator_25kev: {n} events of {gen.energy_kev:g} keV, "
+                               f"{sensor.thickness_um:g} um Si at {sensor.v_bias:g} V, V_dep "
+                               f"{sensor.v_dep:g} V, {G}x{G} pixels of {sensor.pitch_um:g} um; "
+                               f"Fano {gen.fano:g}, noise {gen.noise_kev:g} keV; one ct_generate "
+                               f"launch per step (one wave per event)", "events": n},
+        "carriers_per_s": carriers / wall,
+        "carriers_per_step": carriers // a.steps,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_OP_PEAK / 1e12,
+                     "unit": "Tops/s (vector lane operations)", "frac": achieved / VALU_OP_PEAK,
+                     "traffic": traffic, "traffic_note": traffic_note,
+                     "ops_per_carrier": OPS_PER_CARRIER, "kernel": f"k_gen<{G}>",
+                     "avg_launch_ms": kern_ms / a.steps, "launches": a.steps,
+                     "algorithmic_bytes_per_launch": n * (8 * G * G + 4 * (G * G + 1) + 40)},
+    }
+    if not a.no_cpu_baseline:
+        import oracle
+        import oracle.generator as og
+        oracle.build(force=False)
+        k, t2, chunk = 0, time.perf_counter(), 200
+        while (time.perf_counter() - t2) < a.cpu_seconds and k < n:
+            og.generate(sensor, gen, chunk, first_event_id=k)
+            k += chunk
+        cwall = time.perf_counter() - t2
+        out["cpu_baseline"] = {"value": k / cwall, "unit": "events/s", "cores": 1, "kind": "oracle",
+                               "sample": f"events 0..{k - 1} of generator_25kev ({cwall:.1f} s), "
+                                         f"the oracle's numpy generator on one thread"}
+        print(f"bench: oracle {k / cwall:.1f} events/s", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

@@ -253,6 +253,43 @@ ct_status ct_philox(ct_ctx *c, const uint32_t *counters, int64_t n, uint32_t *wo
 ct_status ct_set_launch(ct_ctx *c, int32_t targets_per_thread, int32_t block_size,
                         int32_t chunk_len);
 
+/* Parameterised event generation (Sec. 4.2): photon events drawn from the
+ * modelling of Sec. 3 instead of simulated.  Per event (id first_event_id + b):
+ *   depth h from the entrance side, exponential with atten_um, conditioned on
+ *   absorption inside the sensor; the drift time t of Eq. 9 for holes from h
+ *   (Jacoboni-Canali hole mu0 and E_c of the context, the field of Eq. 6);
+ *   alpha(t) = p_alpha[0] + p_alpha[1] sqrt(t) + p_alpha[2] t + p_alpha[3] t^2
+ *   (Eq. 10) and beta(t) = 2 + p_beta[0] (t - p_beta[1])^p_beta[2]
+ *   + p_beta[3] exp(p_beta[4] t) (Eq. 11); the carrier count
+ *   N = max(0, floor(E/w + sqrt(fano E/w) g + 1/2)) with g standard normal;
+ *   a sub-pixel shift (x0, y0) uniform over the central pixel; each carrier's
+ *   pixel drawn from the generalized Gaussian of Eq. 8 (scale alpha, shape
+ *   beta, centred on the shift, x and y independent) over the context's
+ *   grid_n x grid_n pixels of pitch_um (outside: the overflow bin); pixel
+ *   energies count * w + noise_kev * normal.
+ * Random draws: Philox counters (0, 0, id, 5) for the depth and shift,
+ * (1, 0, id, 5) for the count's normal, (j, 1, id, 5) for carriers 2j and
+ * 2j + 1, (p / 3, 2, id, 5) for the noise of pixel p, under the context's seed.
+ * Outputs are DEVICE pointers owned by the caller, each nullable:
+ *   energy [n_events][grid_n^2] (keV), counts [n_events][grid_n^2 + 1] (the
+ *   last is the overflow bin), info [n_events][5] = h (um), t (ns), N, x0, y0.
+ * The work is queued on the context's stream; with kernel_ms (nullable, host)
+ * the call waits for it and returns its duration.  Needs grid_n <= 8 and
+ * 0 <= v_dep < v_bias; p_beta[1] < 0; alpha(t) and beta(t) positive for every
+ * drift time of the sensor (CT_EINVAL otherwise).  No seeded batch needed. */
+typedef struct {
+    double energy_kev;  /* photon energy > 0 */
+    double fano;        /* Fano factor >= 0 (0.13 in Sec. 4.2) */
+    double noise_kev;   /* pixel noise sigma >= 0 (0.13 keV in Sec. 4.2) */
+    double atten_um;    /* absorption length of the photons in the sensor > 0 */
+    double p_alpha[4];  /* Eq. 10 */
+    double p_beta[5];   /* Eq. 11 */
+} ct_gen_params;
+
+ct_status ct_generate(ct_ctx *c, const ct_gen_params *g, int64_t n_events,
+                      uint64_t first_event_id, double *energy, int32_t *counts, double *info,
+                      float *kernel_ms);
+
 void ct_destroy(ct_ctx *c);
 
 const char *ct_last_error(void);

@@ -68,6 +68,13 @@ class ct_event_desc(C.Structure):
     ]
 
 
+class ct_gen_params(C.Structure):
+    _fields_ = [
+        ("energy_kev", C.c_double), ("fano", C.c_double), ("noise_kev", C.c_double),
+        ("atten_um", C.c_double), ("p_alpha", C.c_double * 4), ("p_beta", C.c_double * 5),
+    ]
+
+
 class ct_run_stats(C.Structure):
     _fields_ = [
         ("steps", C.c_int64), ("pairs", C.c_uint64), ("n_total", C.c_int64), ("n_active", C.c_int64),
@@ -79,7 +86,7 @@ class ct_run_stats(C.Structure):
 
 EXPORTS = ["ct_init_sensor", "ct_event_carriers", "ct_workspace_bytes", "ct_bind_workspace",
            "ct_seed_events", "ct_step", "ct_collect", "ct_field", "ct_philox", "ct_set_launch",
-           "ct_destroy", "ct_last_error"]
+           "ct_destroy", "ct_last_error", "ct_generate"]
 
 _lib = None
 
@@ -115,6 +122,9 @@ def load(path: str = LIB_PATH):
     L.ct_philox.restype = st
     L.ct_set_launch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
     L.ct_set_launch.restype = st
+    L.ct_generate.argtypes = [C.c_void_p, P(ct_gen_params), C.c_int64, C.c_uint64, C.c_void_p,
+                              C.c_void_p, C.c_void_p, P(C.c_float)]
+    L.ct_generate.restype = st
     L.ct_destroy.argtypes = [C.c_void_p]
     L.ct_destroy.restype = None
     L.ct_last_error.argtypes = []
@@ -250,6 +260,54 @@ def ct_philox(ctx, counters: np.ndarray):
 def ct_set_launch(ctx, targets_per_thread: int = 0, block_size: int = 0, chunk_len: int = 0) -> None:
     _check(load().ct_set_launch(ctx, int(targets_per_thread), int(block_size), int(chunk_len)),
            "ct_set_launch")
+
+
+def make_gen_params(gen) -> ct_gen_params:
+    """ct_gen_params from an object with energy_kev, fano, noise_kev, atten_um,
+    p_alpha[4], p_beta[5]."""
+    return ct_gen_params(float(gen.energy_kev), float(gen.fano), float(gen.noise_kev),
+                         float(gen.atten_um), (C.c_double * 4)(*map(float, gen.p_alpha)),
+                         (C.c_double * 5)(*map(float, gen.p_beta)))
+
+
+def ct_generate(ctx, gen, n_events: int, first_event_id: int, energy_ptr: int, counts_ptr: int,
+                info_ptr: int, timed: bool = False) -> Optional[float]:
+    """Queue the generation of n_events events into caller-owned device
+    buffers (raw pointers, 0 = not wanted); with timed, wait and return the
+    kernel's duration in ms."""
+    ms = C.c_float(0.0)
+    g = make_gen_params(gen)
+    _check(load().ct_generate(ctx, C.byref(g), int(n_events), int(first_event_id),
+                              C.c_void_p(energy_ptr or None), C.c_void_p(counts_ptr or None),
+                              C.c_void_p(info_ptr or None), C.byref(ms) if timed else None),
+           "ct_generate")
+    return float(ms.value) if timed else None
+
+
+def generate(sensor, gen, n_events: int, first_event_id: int = 0, device: int = 0) -> dict:
+    """Generate events on the GPU into torch buffers and return them as numpy
+    arrays: energy [n, G^2], counts [n, G^2 + 1], and h, t, n, x0, y0 [n]."""
+    if not _HAVE_TORCH:
+        raise RuntimeError("generate() allocates its output with torch")
+    G = sensor.grid_n
+    dev = f"cuda:{device}"
+    torch.cuda.set_device(device)
+    energy = torch.empty((n_events, G * G), dtype=torch.float64, device=dev)
+    counts = torch.empty((n_events, G * G + 1), dtype=torch.int32, device=dev)
+    info = torch.empty((n_events, 5), dtype=torch.float64, device=dev)
+    params = make_params(sensor, CT_FP64, stream=torch.cuda.current_stream(device).cuda_stream,
+                         device=device)
+    ctx = ct_init_sensor(params)
+    try:
+        ct_generate(ctx, gen, n_events, first_event_id, energy.data_ptr(), counts.data_ptr(),
+                    info.data_ptr())
+        torch.cuda.synchronize(device)
+    finally:
+        ct_destroy(ctx)
+    inf = info.cpu().numpy()
+    return {"energy": energy.cpu().numpy(), "counts": counts.cpu().numpy().astype(np.int64),
+            "h": inf[:, 0], "t": inf[:, 1], "n": inf[:, 2].astype(np.int64), "x0": inf[:, 3],
+            "y0": inf[:, 4]}
 
 
 def ct_destroy(ctx) -> None:

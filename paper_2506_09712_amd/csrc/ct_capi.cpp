@@ -1012,6 +1012,75 @@ ct_status ct_philox(ct_ctx *c, const uint32_t *counters, int64_t n, uint32_t *wo
     return CT_OK;
 }
 
+ct_status ct_generate(ct_ctx *c, const ct_gen_params *g, int64_t n_events,
+                      uint64_t first_event_id, double *energy, int32_t *counts, double *info,
+                      float *kernel_ms)
+{
+    if (!c) return fail(CT_EINVAL, "ctx is NULL");
+    if (c->broken) return fail(CT_EDEVICE, "context unusable after a device error");
+    if (!g) return fail(CT_EINVAL, "generator parameters are NULL");
+    if (n_events < 0 || n_events > INT32_MAX) return fail(CT_EINVAL, "n_events out of range");
+    const ct_sensor_params &p = c->p;
+    if (p.grid_n > 8) return fail(CT_EINVAL, "the generator supports grids of at most 8 x 8 pixels");
+    if (!(p.v_bias > p.v_dep && p.v_dep >= 0.0))
+        return fail(CT_EINVAL, "the drift time (Eq. 9) needs 0 <= v_dep < v_bias");
+    bool finite = std::isfinite(g->energy_kev) && std::isfinite(g->fano) &&
+                  std::isfinite(g->noise_kev) && std::isfinite(g->atten_um);
+    for (double v : g->p_alpha) finite = finite && std::isfinite(v);
+    for (double v : g->p_beta) finite = finite && std::isfinite(v);
+    if (!finite) return fail(CT_EINVAL, "generator parameters must be finite");
+    if (!(g->energy_kev > 0.0) || g->fano < 0.0 || g->noise_kev < 0.0 || !(g->atten_um > 0.0))
+        return fail(CT_EINVAL, "need energy_kev > 0, fano >= 0, noise_kev >= 0, atten_um > 0");
+    if (!(g->p_beta[1] < 0.0)) return fail(CT_EINVAL, "p_beta[1] must be < 0 (Eq. 11 at t >= 0)");
+    ct::GenDev d{};
+    const double H = p.thickness_um;
+    d.H = H;
+    d.e_entrance = (p.v_bias - p.v_dep) / H;
+    d.e_pixels = (p.v_bias + p.v_dep) / H;
+    d.k = 2.0 * p.v_dep / (H * H);
+    double mu0, ec, beta;
+    hole_mobility_params(p, mu0, ec, beta);
+    d.inv_mu0 = 1.0 / mu0;
+    d.inv_ec = 1.0 / ec;
+    d.atten = g->atten_um;
+    d.keep = -std::expm1(-H / g->atten_um);
+    d.mean_n = 1000.0 * g->energy_kev / p.pair_energy_ev;
+    d.sd_n = std::sqrt(g->fano * d.mean_n);
+    d.w_kev = p.pair_energy_ev / 1000.0;
+    d.noise = g->noise_kev;
+    d.pitch = p.pitch_um;
+    for (int i = 0; i < 4; ++i) d.pa[i] = g->p_alpha[i];
+    for (int i = 0; i < 5; ++i) d.pb[i] = g->p_beta[i];
+    d.grid_n = p.grid_n;
+    d.key0 = (uint32_t)p.seed;
+    d.key1 = (uint32_t)(p.seed >> 32);
+    d.first_event_id = first_event_id;
+    // alpha(t) and beta(t) must be positive over every drift time that occurs
+    const double t_max = d.k > 0.0
+                             ? (std::log(d.e_pixels / d.e_entrance) / d.k + H * d.inv_ec) * d.inv_mu0
+                             : H * (1.0 / d.e_entrance + d.inv_ec) * d.inv_mu0;
+    for (int i = 0; i <= 1000; ++i) {
+        const double t = t_max * i / 1000.0;
+        const double a = d.pa[0] + d.pa[1] * std::sqrt(t) + d.pa[2] * t + d.pa[3] * t * t;
+        const double b = 2.0 + d.pb[0] * std::pow(t - d.pb[1], d.pb[2]) + d.pb[3] * std::exp(d.pb[4] * t);
+        if (!(a > 0.0) || !(b > 0.0) || !std::isfinite(a) || !std::isfinite(b))
+            return fail(CT_EINVAL, "alpha(t) = %g, beta(t) = %g at t = %g ns: both must be positive "
+                                   "for every drift time in [0, %g] ns", a, b, t, t_max);
+    }
+    if (n_events == 0) return CT_OK;
+    ct_status st = set_device(c);
+    if (st != CT_OK) return st;
+    hipStream_t sm = c->stream;
+    if (kernel_ms) CT_HIP(hipEventRecord(c->ev_a, sm));
+    CT_HIP(ct::launch_gen(d, n_events, energy, counts, info, sm));
+    if (kernel_ms) {
+        CT_HIP(hipEventRecord(c->ev_b, sm));
+        CT_HIP(hipEventSynchronize(c->ev_b));
+        CT_HIP(hipEventElapsedTime(kernel_ms, c->ev_a, c->ev_b));
+    }
+    return CT_OK;
+}
+
 void ct_destroy(ct_ctx *c)
 {
     if (!c) return;

@@ -48,9 +48,9 @@ __device__ __forceinline__ double to_unit(uint32_t w)
 }
 
 // Three standard normals from one Philox block (Box-Muller on (u0,u1), (u2,u3)).
-__device__ void normals3(const DevParams &dp, Ctr ctr, double n[3])
+__device__ inline void normals3(uint32_t key0, uint32_t key1, Ctr ctr, double n[3])
 {
-    const Ctr w = philox10(ctr, dp.key0, dp.key1);
+    const Ctr w = philox10(ctr, key0, key1);
     const double u0 = to_unit(w.c0), u1 = to_unit(w.c1);
     const double u2 = to_unit(w.c2), u3 = to_unit(w.c3);
     const double ra = sqrt(-2.0 * log(u0));
@@ -60,6 +60,11 @@ __device__ void normals3(const DevParams &dp, Ctr ctr, double n[3])
     n[0] = ra * c1;
     n[1] = ra * s1;
     n[2] = rb * cospi(2.0 * u3);
+}
+
+__device__ __forceinline__ void normals3(const DevParams &dp, Ctr ctr, double n[3])
+{
+    normals3(dp.key0, dp.key1, ctr, n);
 }
 
 // ------------------------------------------------------------ memory order
@@ -162,7 +167,7 @@ __device__ __forceinline__ int pixel_bin(const DevParams &dp, double x, double y
 
 // A carrier reaches an electrode: endpoint and step by carrier; holes are
 // counted in the pixel grid (with an overflow bin), electrons are not.
-__device__ void collect(const DevParams &dp, const DevBatch &bt, int b, int carrier, bool electron,
+__device__ inline void collect(const DevParams &dp, const DevBatch &bt, int b, int carrier, bool electron,
                         double x, double y, double z, int64_t step)
 {
     bt.out_xyz[3 * (int64_t)carrier + 0] = x;

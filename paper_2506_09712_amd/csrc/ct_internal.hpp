@@ -116,6 +116,21 @@ struct LaunchCfg {
     int chunk;     // source chunk length (a multiple of bs; events longer than this are split)
 };
 
+// Parameters of the event generator (Sec. 4.2), precomputed on the host.
+struct GenDev {
+    double H;                    // thickness (um)
+    double e_entrance, e_pixels; // drift field magnitude at the entrance side and the pixels (V/um)
+    double k;                    // its slope along the drift (V/um^2), Eq. 6
+    double inv_mu0, inv_ec;      // hole Jacoboni-Canali parameters (Eq. 9)
+    double atten, keep;          // absorption length (um), 1 - exp(-H / atten)
+    double mean_n, sd_n;         // E / w and sqrt(F E / w)
+    double w_kev, noise, pitch;  // pair energy (keV), pixel noise sigma (keV), pixel pitch (um)
+    double pa[4], pb[5];         // Eqs. 10 and 11
+    int32_t grid_n;
+    uint32_t key0, key1;
+    uint64_t first_event_id;
+};
+
 // Kernel launchers (ct_kernels.hip).  All return the launch status.
 hipError_t launch_seed(const DevParams &dp, const DevBatch &bt, hipStream_t s);
 hipError_t launch_compact(const DevParams &dp, const DevBatch &bt, hipStream_t s);
@@ -130,6 +145,10 @@ hipError_t launch_summary(const DevBatch &bt, Sched *sc, hipStream_t s);
 hipError_t launch_sph(const DevParams &dp, const DevBatch &bt, double *scratch, int64_t max_steps,
                       int field_only, double *field_out, hipStream_t s);
 int sph_block();
+// Event generator (ct_gen.hip): n_events events, one wave each; outputs
+// (device, nullable) energy [n][G^2], counts [n][G^2 + 1], info [n][5].
+hipError_t launch_gen(const GenDev &g, int64_t n_events, double *energy, int32_t *counts,
+                      double *info, hipStream_t s);
 int run_occupancy(const LaunchCfg &cfg, int fp32);
 bool launch_supported(int kt, int bs);
 hipError_t launch_scatter_alive(const DevBatch &bt, int n_max, hipStream_t s);

@@ -16,4 +16,6 @@ from .events import (  # noqa: F401
     gamma_60kev,
     track_200kev,
     explicit_batch,
+    GenParams,
+    generator_25kev,
 )

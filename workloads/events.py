@@ -308,6 +308,35 @@ def batch_8kev_eh(n_events: int = 256, seed: int = 0) -> tuple:
     return s.replace(electrons=True), b
 
 
+@dataclass
+class GenParams:
+    """Inputs of the parameterised event generation (Sec. 4.2): photon energy
+    (keV), Fano factor, pixel noise sigma (keV), absorption length (um), and
+    the parameters of alpha(t) (Eq. 10) and beta(t) (Eq. 11)."""
+    energy_kev: float
+    fano: float = 0.13
+    noise_kev: float = 0.13
+    atten_um: float = 1000.0
+    p_alpha: tuple = (1.0, 0.0, 0.0, 0.0)
+    p_beta: tuple = (0.0, -1.0, -1.0, 0.0, 0.0)
+
+
+def generator_25kev(n_events: int = 1_000_000, seed: int = 0) -> tuple:
+    """One million 25 keV events in the sensor of the paper's modelling example
+    (320 um, 150 V, V_dep 29.6 V, 34.7 C) with 5 x 5 pixels of 25 um.  alpha(t)
+    and beta(t) are fits of Eqs. 10 and 11 to the library's own brute-force
+    simulation of that sensor (paper_2506_09712_amd.model.parameterise: 32
+    depths from 5 to 315 um, 10 events each, FP32 field, dt 0.05 ns, Eq. 2
+    width); the absorption length is the stand-in law attenuation_um(25 keV),
+    not tabulated silicon data."""
+    s = Sensor(thickness_um=320.0, v_bias=150.0, v_dep=29.6, temperature_k=307.85, seed=seed)
+    g = GenParams(energy_kev=25.0, fano=0.13, noise_kev=0.13,
+                  atten_um=float(attenuation_um(np.array([25.0]))[0]),
+                  p_alpha=(1.38085, 2.69548, -0.101361, 0.000928956),
+                  p_beta=(1.33696, -2.75936, -0.460003, -0.462949, -2.18759))
+    return s, g, n_events
+
+
 WORKLOADS: Dict[str, Callable[..., tuple]] = {
     "single_8kev": single_8kev,
     "batch_8kev": batch_8kev,
