@@ -183,6 +183,23 @@ __device__ int claim(const DevQueue &dq, uint32_t n_events, uint64_t idle_ticks,
     return 1;
 }
 
+// Wave priority while a workgroup computes an item of an event whose drifting
+// carriers have their centroid at height z_ref above the pixel plane.  Holes
+// drift towards the pixels at similar speeds, so the deeper the centroid, the
+// more steps the event has left, and the sooner its items should finish when
+// workgroups share a SIMD: the four levels are the quarters of the sensor
+// thickness.  (With electrons the centroid counts them too, which only blurs
+// the ordering.)  Issue priority changes timing only, never results.
+__device__ __forceinline__ void set_item_priority(double z_ref, double H)
+{
+    const int level = __builtin_amdgcn_readfirstlane(
+        z_ref > 0.75 * H ? 3 : (z_ref > 0.5 * H ? 2 : (z_ref > 0.25 * H ? 1 : 0)));
+    if (level == 3) __builtin_amdgcn_s_setprio(3);
+    else if (level == 2) __builtin_amdgcn_s_setprio(2);
+    else if (level == 1) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
 template <int KT, int BS, bool F32>
 __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue &dq,
                          const RunArgs &ra, void *lds)
@@ -215,6 +232,7 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
         const int nh = it.nh;  // the first nh slots hold holes, the rest electrons
         const int base = bt.off[b];
         const int n0 = bt.off[b + 1] - base;
+        set_item_priority(bt.ref[4 * b + 2], dp.H);
         int len = n, chunks = 1;
         if (repulsion) event_chunks(n, BS, ra.chunk, len, chunks);
         const int t0 = it.tile * T;
@@ -318,6 +336,9 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
             }
         }
 
+        // the rest of the item (partials, update, compaction, publication)
+        // holds up every later step of its event: top priority
+        __builtin_amdgcn_s_setprio(3);
         if (chunks > 1) {
             // this chunk's partial field; the tile's last chunk sums them all
             const int64_t po = dq.part_off[b] + 3 * (int64_t)it.chunk * n0;
