@@ -234,7 +234,10 @@ def main():
         n_plain = min(a.plain_events, batch.n_events)
 
         def rate(prec, plain):
-            sim = ct.Simulator(sensor, prec, device=0, options=tune)
+            # one event at a time: the autotuner's launch for a single event
+            # (short chunks, more work items per step) unless one is pinned
+            opts = ct.CT_OPT_AUTOTUNE if (plain and not launch) else tune
+            sim = ct.Simulator(sensor, prec, device=0, options=opts)
             evs = [batch.event(e) for e in range(n_plain)] if plain else [batch]
             simulate(ct, sim, evs[0])
             torch.cuda.synchronize()

@@ -253,19 +253,23 @@ ct_status shape_of(const ct_sensor_params &p, const ct_event_desc *ev, int32_t B
 }
 
 // Launch configuration of a new context (ct_set_launch overrides it): one
-// target per thread, 256-thread workgroups, sources in chunks of 768.
+// target per thread, 256-thread workgroups, sources in chunks of 1280 (the
+// fastest whole-run length on batches of 2222- to 6111-hole events; longer
+// chunks mean fewer partial fields per step, shorter ones more work items to
+// spread over the workgroups).
 ct::LaunchCfg default_cfg(const ct_sensor_params &p)
 {
     (void)p;
-    return ct::LaunchCfg{1, 256, 768};
+    return ct::LaunchCfg{1, 256, 1280};
 }
 
-// Tickets the work queue holds per run: about 512 steps of the batch at its
-// initial size (the environment variable CT_QUEUE_STEPS overrides the 512),
-// at least one step, at most 2^25 tickets; a run that fills it parks the
-// events it could not queue and the host runs again.
-constexpr int64_t kQueueSteps = 512;
-constexpr int64_t kQueueMax = int64_t(1) << 25;
+// Tickets the work queue holds per run: about 1024 steps of the batch at its
+// initial size (the environment variable CT_QUEUE_STEPS overrides the 1024),
+// at least one step, at most 2^26 tickets (36 B each: 2.4 GB at most); a run
+// that fills it parks the events it could not queue and the host runs again,
+// which costs a drain of the GPU per extra run.
+constexpr int64_t kQueueSteps = 1024;
+constexpr int64_t kQueueMax = int64_t(1) << 26;
 
 int64_t queue_steps()
 {
@@ -334,7 +338,7 @@ struct ct_ctx {
     int device = 0;
     hipStream_t stream = nullptr;  // the caller's stream, or one of ours
     bool own_stream = false;
-    ct::LaunchCfg cfg{1, 256, 768};
+    ct::LaunchCfg cfg{1, 256, 1280};
     int cu_count = 0;
     int grid = 0;  // resident workgroups of the run kernel for cfg
 
@@ -595,8 +599,11 @@ ct_status autotune(ct_ctx *c)
     if (!cached) {
         st = ensure_field_buf(c, c->shape.N);
         if (st != CT_OK) return st;
-        const std::vector<ct::LaunchCfg> cand = {{1, 256, 512}, {1, 256, 768}, {1, 256, 1024},
-                                                 {1, 128, 512}, {2, 256, 768}};
+        // long chunks suit large batches (fewer partial fields), short chunks
+        // and small tiles suit a few events (more work items per step)
+        const std::vector<ct::LaunchCfg> cand = {
+            {1, 256, 512},  {1, 256, 768},  {1, 256, 1280}, {1, 256, 1536},
+            {1, 256, 2304}, {1, 128, 256},  {1, 128, 512},  {2, 256, 1280}};
         float best_ms = 1e30f;
         const double ms0 = c->field_ms;
         const int64_t l0 = c->field_launches;

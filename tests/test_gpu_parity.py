@@ -418,7 +418,7 @@ def test_runs_bitwise_reproducible_and_timed(ct):
             np.testing.assert_array_equal(g["cstep"], r["cstep"])
             np.testing.assert_array_equal(g["pix"], r["pix"])
         assert t["stats"].field_launches == 1 and t["stats"].field_kernel_ms > 0
-        assert g["stats"].workgroups > 0 and g["stats"].chunk_len == 768
+        assert g["stats"].workgroups > 0 and g["stats"].chunk_len == 1280
 
 
 def test_full_work_queue_parks_and_resumes(ct, monkeypatch):
@@ -445,7 +445,7 @@ def test_autotuned_launch_matches_oracle(ct):
             g = sim.run(b)
         st = g["stats"]
         assert st.block_size in (128, 256) and st.targets_per_thread in (1, 2)
-        assert st.chunk_len in (512, 768, 1024)
+        assert st.chunk_len in (256, 512, 768, 1280, 1536, 2304)
         for e in (0, 31, 63):
             o = oracle.run(s, b.event(e))
             if prec == FP64:
