@@ -282,16 +282,19 @@ int64_t queue_steps()
 // Work queue, completion counters and partial-field buffer of a batch for a
 // launch configuration, in one device allocation.
 struct QueueLayout {
-    size_t sched, q, seq, tiles_left, chunks_left, tile_base, part_off, part, total;
+    size_t sched, q, seq, tiles_left, chunks_left, tile_base, part_off, part, tk_off, grp_off, grp,
+        single, total;
     uint32_t cap;
-    std::vector<int32_t> tile_base_h;
-    std::vector<int64_t> part_off_h;
+    int32_t n_tickets;
+    std::vector<int32_t> tile_base_h, tk_off_h, single_h;
+    std::vector<int64_t> part_off_h, grp_off_h;
 };
 
-// The spherical model runs without a queue: it keeps only the control block
-// (and minimal arrays).
+// The spherical model runs without a work queue: it keeps the control block,
+// its tickets (one per workgroup of each event; sph_max_group bounds the
+// workgroups sharing an event) and the state of shared events.
 QueueLayout make_queue_layout(const BatchShape &s, const ct::LaunchCfg &cfg, bool repulsion,
-                              bool spherical)
+                              bool spherical, int sph_max_group)
 {
     QueueLayout Q{};
     const int64_t T = (int64_t)cfg.kt * cfg.bs;
@@ -309,6 +312,15 @@ QueueLayout make_queue_layout(const BatchShape &s, const ct::LaunchCfg &cfg, boo
         Q.part_off_h[b + 1] = Q.part_off_h[b] + (chunks > 1 ? 3 * n0 * chunks : 0);
         items += tiles * chunks;
     }
+    Q.tk_off_h.assign(s.B + 1, 0);
+    Q.grp_off_h.assign(s.B + 1, 0);
+    for (int64_t b = 0; b < s.B; ++b) {
+        const int G = spherical && repulsion ? ct::sph_group(s.n[b], sph_max_group) : 1;
+        Q.tk_off_h[b + 1] = Q.tk_off_h[b] + G;
+        Q.grp_off_h[b + 1] = Q.grp_off_h[b] + (G > 1 ? (int64_t)ct::sph_group_bytes(G) : 0);
+        if (G == 1) Q.single_h.push_back((int32_t)b);
+    }
+    Q.n_tickets = Q.tk_off_h[s.B];
     int64_t cap = std::max<int64_t>(items, std::min<int64_t>(items * queue_steps(), kQueueMax));
     cap = std::max<int64_t>(cap, 1);
     Q.cap = (uint32_t)cap;
@@ -326,6 +338,10 @@ QueueLayout make_queue_layout(const BatchShape &s, const ct::LaunchCfg &cfg, boo
     Q.tile_base = take(sizeof(int32_t) * (s.B + 1));
     Q.part_off = take(sizeof(int64_t) * (s.B + 1));
     Q.part = take(sizeof(double) * Q.part_off_h[s.B]);
+    Q.tk_off = take(sizeof(int32_t) * (s.B + 1));
+    Q.grp_off = take(sizeof(int64_t) * (s.B + 1));
+    Q.grp = take((size_t)Q.grp_off_h[s.B]);
+    Q.single = take(sizeof(int32_t) * Q.single_h.size());
     Q.total = o;
     return Q;
 }
@@ -341,6 +357,7 @@ struct ct_ctx {
     ct::LaunchCfg cfg{1, 256, 1280};
     int cu_count = 0;
     int grid = 0;  // resident workgroups of the run kernel for cfg
+    int grid_shared = 0;  // spherical model: workgroups over the events shared by several
 
     // device workspace (the batch)
     void *ws = nullptr;
@@ -429,7 +446,14 @@ ct_status prepare_queue(ct_ctx *c, const ct::LaunchCfg &cfg)
 {
     const bool repulsion = (c->p.physics_flags & CT_REPULSION) != 0;
     const bool spherical = (c->p.physics_flags & CT_SPHERICAL) != 0;
-    QueueLayout Q = make_queue_layout(c->shape, cfg, repulsion, spherical);
+    int sph_cap = 0;
+    if (spherical) {
+        const int occ = ct::sph_occupancy();
+        if (occ <= 0) return fail(CT_EDEVICE, "spherical kernel occupancy query failed");
+        sph_cap = occ * c->cu_count;
+        if (sph_cap < 2) return fail(CT_EDEVICE, "fewer than 2 resident spherical workgroups");
+    }
+    QueueLayout Q = make_queue_layout(c->shape, cfg, repulsion, spherical, sph_cap);
     hipStream_t sm = c->stream;
     if (Q.total > c->qbuf_bytes) {
         if (c->qbuf) {
@@ -459,16 +483,31 @@ ct_status prepare_queue(ct_ctx *c, const ct::LaunchCfg &cfg)
     d.tile_base = at<int32_t>(c->qbuf, Q.tile_base);
     d.part = at<double>(c->qbuf, Q.part);
     d.part_off = at<int64_t>(c->qbuf, Q.part_off);
+    d.tk_off = at<int32_t>(c->qbuf, Q.tk_off);
+    d.grp_off = at<int64_t>(c->qbuf, Q.grp_off);
+    d.grp = at<char>(c->qbuf, Q.grp);
+    d.n_tickets = Q.n_tickets;
+    d.single = at<int32_t>(c->qbuf, Q.single);
     if (c->shape.B > 0) {
         CT_HIP(hipMemcpyAsync((void *)d.tile_base, Q.tile_base_h.data(),
                               sizeof(int32_t) * (c->shape.B + 1), hipMemcpyHostToDevice, sm));
         CT_HIP(hipMemcpyAsync((void *)d.part_off, Q.part_off_h.data(),
                               sizeof(int64_t) * (c->shape.B + 1), hipMemcpyHostToDevice, sm));
+        CT_HIP(hipMemcpyAsync((void *)d.tk_off, Q.tk_off_h.data(),
+                              sizeof(int32_t) * (c->shape.B + 1), hipMemcpyHostToDevice, sm));
+        CT_HIP(hipMemcpyAsync((void *)d.grp_off, Q.grp_off_h.data(),
+                              sizeof(int64_t) * (c->shape.B + 1), hipMemcpyHostToDevice, sm));
+        if (!Q.single_h.empty())
+            CT_HIP(hipMemcpyAsync((void *)d.single, Q.single_h.data(),
+                                  sizeof(int32_t) * Q.single_h.size(), hipMemcpyHostToDevice, sm));
         CT_HIP(hipStreamSynchronize(sm));  // host vectors go out of scope
     }
     c->dq = d;
     if (spherical) {
-        c->grid = (int)c->shape.B;  // one workgroup per event
+        // resident workgroups claiming the tickets (at least the largest group)
+        const int single = (int)Q.single_h.size();
+        c->grid = single;  // one workgroup per single-workgroup event
+        c->grid_shared = std::min<int>(Q.n_tickets - single, sph_cap);
         return CT_OK;
     }
     const int occ = ct::run_occupancy(cfg, c->p.precision == CT_FP32);
@@ -522,8 +561,8 @@ ct_status run_sph(ct_ctx *c, int64_t max_steps, int field_only, double *field_ou
 {
     hipStream_t sm = c->stream;
     if (timing) CT_HIP(hipEventRecord(c->ev_a, sm));
-    CT_HIP(ct::launch_sph(c->dp, c->bt, at<double>(c->ws, c->L.sph), max_steps, field_only,
-                          field_out, sm));
+    CT_HIP(ct::launch_sph(c->dp, c->bt, c->dq, at<double>(c->ws, c->L.sph), c->grid,
+                          c->grid_shared, max_steps, field_only, field_out, sm));
     if (timing) CT_HIP(hipEventRecord(c->ev_b, sm));
     CT_HIP(ct::launch_summary(c->bt, c->dq.sc, sm));
     CT_HIP(hipMemcpyAsync(c->h_sched, c->dq.sc, sizeof(ct::Sched), hipMemcpyDeviceToHost, sm));
@@ -533,6 +572,11 @@ ct_status run_sph(ct_ctx *c, int64_t max_steps, int field_only, double *field_ou
         CT_HIP(hipEventElapsedTime(&ms, c->ev_a, c->ev_b));
         c->field_ms += ms;
         c->field_launches += 1;
+    }
+    if (c->h_sched->error.v) {
+        c->broken = true;
+        return fail(CT_EDEVICE, "spherical kernel stopped: the workgroups of a shared event did not "
+                                "meet within 10 s");
     }
     return CT_OK;
 }
@@ -958,7 +1002,7 @@ ct_status ct_collect(ct_ctx *c, int32_t *pixel_counts, double *xyz, int32_t *col
         r.field_kernel_ms = c->field_ms;
         r.step_wall_ms = c->step_wall_ms;
         r.targets_per_thread = spherical(c) ? 1 : c->cfg.kt;
-        r.block_size = spherical(c) ? ct::sph_block() : c->cfg.bs;
+        r.block_size = spherical(c) ? ct::kSphBlock : c->cfg.bs;
         r.chunk_len = spherical(c) ? 0 : c->cfg.chunk;
         r.workgroups = c->grid;
         *stats = r;

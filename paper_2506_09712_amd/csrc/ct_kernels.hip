@@ -700,6 +700,8 @@ uint64_t idle_ticks()
 
 // ------------------------------------------------------------------ launchers
 
+uint64_t run_idle_ticks() { return idle_ticks(); }
+
 hipError_t launch_seed(const DevParams &dp, const DevBatch &bt, hipStream_t s)
 {
     if (bt.n_total <= 0) return hipSuccess;

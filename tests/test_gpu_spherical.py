@@ -204,3 +204,43 @@ def test_spherical_error_paths(ct):
     with pytest.raises(ct.CtError) as e:
         ct.Simulator(_sph(Sensor(electrons=True)), FP64)
     assert e.value.status == -1
+
+
+def test_shared_events_mixed_batch(ct):
+    """Events above 8192 holes are shared by several workgroups (contiguous
+    slices, barriers between the ranking phases); smaller ones keep one.  A
+    batch mixing both, with an empty and a one-hole event, meets the oracle:
+    exact steps and pixel counts, FP64 endpoints within 0.01 um."""
+    sizes = [9000, 0, 1, 2600, 20000, 8192, 8193]
+    clouds = _clouds(sizes, 21)
+    s = _sph(Sensor(seed=6))
+    b = explicit_batch(clouds, first_event_id=300)
+    o = oracle.run(s, b)
+    g = gpu_run(ct, s, b, FP64)
+    assert_fp64_parity(g, o, "shared spherical batch")
+    np.testing.assert_array_equal(g["steps"], o["steps"])
+    np.testing.assert_array_equal(g["pix"], o["pix"])
+    assert g["pairs"] == o["pairs"] and g["hole_steps"] == o["hole_steps"]
+
+
+def test_shared_event_resume_batch_independent(ct):
+    """A shared event (16,667 holes) gives the same bits when stepped in calls
+    of 29 steps, alone or in a batch with other events, and in a CT_FP32
+    context."""
+    s, b = gamma_60kev(seed=3)
+    s = _sph(s)
+    b = b.head(3)
+    ref = gpu_run(ct, s, b, FP64)
+    with ct.Simulator(s, FP64) as sim:
+        sim.seed(b)
+        while True:
+            st, _, _ = sim.step(29)
+            if st == 0:
+                break
+            assert st == -5
+        r = sim.collect()
+    for k in ("xyz", "cstep", "pix", "steps"):
+        np.testing.assert_array_equal(r[k], ref[k])
+    np.testing.assert_array_equal(gpu_run(ct, s, b, FP32)["xyz"], ref["xyz"])
+    alone = gpu_run(ct, s, b.event(1), FP64)
+    np.testing.assert_array_equal(alone["xyz"], _event_slice(ref, 1)["xyz"])
