@@ -354,8 +354,9 @@ def generator(a, ct, torch, kw):
 
 
 def spherical(a, ct, torch, sensor, batch, n_holes):
-    """The simplified spherical model on the same workload: one k_sph launch
-    per run (one workgroup per event), FP64."""
+    """The simplified spherical model on the same workload, FP64: per run one
+    k_sph_single launch (one workgroup per event) and, for events of more than
+    8192 holes, one k_sph_shared launch (a group of workgroups per event)."""
     if sensor.electrons:
         raise SystemExit("the spherical model simulates holes only")
     sensor = sensor.replace(spherical=True)
@@ -373,6 +374,7 @@ def spherical(a, ct, torch, sensor, batch, n_holes):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = r["stats"]
+    shared = int(r["n"].max(initial=0)) > 8192
     sim.close()
     events_per_s = batch.n_events * a.steps / wall
     per_launch = hsteps / max(launches, 1)
@@ -389,7 +391,8 @@ def spherical(a, ct, torch, sensor, batch, n_holes):
         "config": {"workload": f"{a.workload}: {batch.n_events} events, {n_holes} holes, "
                                f"{sensor.thickness_um:g} um Si at {sensor.v_bias:g} V, "
                                f"dt {sensor.dt_ns:g} ns; simplified spherical model (Eq. 7), FP64; "
-                               f"one workgroup per event for all of its steps",
+                               f"one workgroup per event for all of its steps (a group of "
+                               f"workgroups per event of more than 8192 holes)",
                    "events": batch.n_events, "holes": n_holes,
                    "launch": {"block": st.block_size, "workgroups": st.workgroups}},
         "hole_updates_per_s": hsteps / wall,
@@ -399,7 +402,8 @@ def spherical(a, ct, torch, sensor, batch, n_holes):
                      "frac": achieved / HBM_PEAK if achieved else None,
                      "traffic": traffic, "traffic_note": traffic_note,
                      "algorithmic_bytes_per_launch": ALG_BYTES_PER_HOLE_STEP * per_launch,
-                     "hole_steps_per_launch": per_launch, "kernel": "k_sph",
+                     "hole_steps_per_launch": per_launch,
+                     "kernel": "k_sph_single+k_sph_shared" if shared else "k_sph_single",
                      "avg_launch_ms": kern_ms / max(launches, 1), "launches": launches},
     }
     if not a.no_cpu_baseline:

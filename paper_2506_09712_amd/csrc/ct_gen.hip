@@ -63,14 +63,19 @@ __device__ double ggd_cdf(double x, double alpha, double beta)
     return x < 0.0 ? 0.5 - p : 0.5 + p;
 }
 
-// Column (row) of a draw u: the pixel i with cdf[i] <= u < cdf[i + 1]; -1 or
-// G outside the grid.  cdf is non-decreasing.
+// Column (row) of a draw: the pixel i with cdf[i] <= u < cdf[i + 1], -1 or G
+// outside the grid, for the uniform u = (w + 0.5) 2^-32 of a Philox word w.
+// Compared in the word's own scale: with t = cdf 2^32 - 0.5 (exact in FP64
+// for cdf in [0, 1], and for cdf < 1/4 only its sign matters), cdf <= u
+// exactly when t <= w, so each edge costs one conversion-free compare.
+// t (the scaled edges) is non-decreasing.
 template <int G>
-__device__ __forceinline__ int pixel_of(const double (&cdf)[G + 1], double u)
+__device__ __forceinline__ int pixel_of(const double (&t)[G + 1], uint32_t w)
 {
+    const double wd = (double)w;
     int i = -1;
 #pragma unroll
-    for (int e = 0; e <= G; ++e) i += cdf[e] <= u ? 1 : 0;
+    for (int e = 0; e <= G; ++e) i += t[e] <= wd ? 1 : 0;
     return i;
 }
 
@@ -112,11 +117,11 @@ __global__ __launch_bounds__(64) void k_gen(GenDev g, int64_t n_events, double *
     }
     for (int i = lane; i < 64 * stride; i += 64) hist[i] = 0;
     __syncthreads();
-    double cx[G + 1], cy[G + 1];
+    double cx[G + 1], cy[G + 1];  // edge CDFs in the scale of a Philox word
 #pragma unroll
     for (int e = 0; e <= G; ++e) {
-        cx[e] = cdf[e];
-        cy[e] = cdf[G + 1 + e];
+        cx[e] = fma(cdf[e], 4294967296.0, -0.5);
+        cy[e] = fma(cdf[G + 1 + e], 4294967296.0, -0.5);
     }
     int32_t *mine = hist + lane * stride;
     // carriers 2j and 2j + 1 share Philox block (j, 1, event, 5)
@@ -124,12 +129,12 @@ __global__ __launch_bounds__(64) void k_gen(GenDev g, int64_t n_events, double *
     for (int j = lane; j < pairs; j += 64) {
         const Ctr c = philox10(Ctr{(uint32_t)j, 1u, eid, kDomainGenerator}, g.key0, g.key1);
         {
-            const int col = pixel_of<G>(cx, to_unit(c.c0)), row = pixel_of<G>(cy, to_unit(c.c1));
+            const int col = pixel_of<G>(cx, c.c0), row = pixel_of<G>(cy, c.c1);
             const bool in = (unsigned)col < (unsigned)G && (unsigned)row < (unsigned)G;
             mine[in ? row * G + col : G * G] += 1;
         }
         if (2 * j + 1 < n) {
-            const int col = pixel_of<G>(cx, to_unit(c.c2)), row = pixel_of<G>(cy, to_unit(c.c3));
+            const int col = pixel_of<G>(cx, c.c2), row = pixel_of<G>(cy, c.c3);
             const bool in = (unsigned)col < (unsigned)G && (unsigned)row < (unsigned)G;
             mine[in ? row * G + col : G * G] += 1;
         }
