@@ -90,11 +90,15 @@ typedef enum { CT_MOB_JACOBONI = 0, CT_MOB_CONSTANT = 1 } ct_mobility;
  * c being the mean position of the event's drifting holes at the step start
  * and Q_i the number of them strictly closer to c than i (Q_i = 0: no
  * field).  Holes only (with CT_ELECTRONS: CT_EINVAL).  It is evaluated in
- * FP64 whatever the precision, one workgroup per event runs all of the
- * event's steps of a ct_step call, and the launch configuration
- * (ct_set_launch) has no effect.  The enclosed counts come from a counting
- * sort over 8192 bins per event and step; a bin holding many holes at nearly
- * the same distance costs time quadratic in its size. */
+ * FP64 whatever the precision, and the launch configuration (ct_set_launch)
+ * has no effect.  One workgroup runs all of an event's steps of a ct_step
+ * call; an event of more than 8192 holes at seeding is shared by
+ * ceil(n / 2560) workgroups (at most 32), a number fixed by the event alone,
+ * so results do not depend on the batch.  The enclosed counts come from a
+ * counting sort over 8192 bins per event and step; a bin holding many holes
+ * at nearly the same distance costs time quadratic in its size.  A shared
+ * event whose workgroups fail to meet for 10 s ends the call with
+ * CT_EDEVICE. */
 enum { CT_REPULSION = 1u, CT_DRIFT = 2u, CT_DIFFUSION = 4u, CT_ELECTRONS = 8u, CT_SPHERICAL = 16u };
 
 /* options bits */
