@@ -83,7 +83,7 @@ CSRC = os.path.join(ROOT, "paper_2506_09712_amd", "csrc")
 # the sources each kernel is built from, and its committed counter summary
 KERNEL_SOURCES = {
     "pairs": ("ct_kernels.hip", "ct_device.hpp", "ct_internal.hpp"),
-    "spherical": ("ct_sph.hip", "ct_device.hpp", "ct_internal.hpp"),
+    "spherical": ("ct_sph.hip", "ct_sph_layout.hpp", "ct_device.hpp", "ct_internal.hpp"),
     "generator": ("ct_gen.hip", "ct_device.hpp", "ct_internal.hpp"),
 }
 TRAFFIC_PROFILES = {

@@ -93,7 +93,7 @@ typedef enum { CT_MOB_JACOBONI = 0, CT_MOB_CONSTANT = 1 } ct_mobility;
  * FP64 whatever the precision, and the launch configuration (ct_set_launch)
  * has no effect.  One workgroup runs all of an event's steps of a ct_step
  * call; an event of more than 8192 holes at seeding is shared by
- * ceil(n / 2560) workgroups (at most 32), a number fixed by the event alone,
+ * ceil(n / 5120) workgroups (at most 32), a number fixed by the event alone,
  * so results do not depend on the batch.  The enclosed counts come from a
  * counting sort over 8192 bins per event and step; a bin holding many holes
  * at nearly the same distance costs time quadratic in its size.  A shared

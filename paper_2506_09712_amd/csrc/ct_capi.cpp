@@ -19,6 +19,7 @@
 
 #include "ct.h"
 #include "ct_internal.hpp"
+#include "ct_sph_layout.hpp"
 
 namespace {
 

@@ -117,77 +117,6 @@ struct DevQueue {
     const int32_t *single;     // the events run by one workgroup, in batch order
 };
 
-// ------------------------------------------------ simplified spherical model
-
-// One workgroup of kSphBlock threads ranks the holes of an event by distance
-// from its centre with a counting sort over kSphBins bins.  An event of more
-// than kSphGroupMin holes at seeding is shared by sph_group(n0) workgroups,
-// each owning a contiguous slice of its drifting holes (at most about
-// kSphSlice); the workgroups of an event meet at barriers on a counter of
-// their own.  The group size depends on the event's seeded size alone (and
-// on the device's resident capacity), so an event's result does not depend on
-// its batch.
-constexpr int kSphBlock = 512;
-constexpr int kSphBins = 8192;
-constexpr int kSphGroupMin = 8192;
-constexpr int kSphSlice = 2560;
-constexpr int kSphMaxGroup = 32;
-
-// Workgroups of an event of n0 holes at seeding (with repulsion): 1 up to
-// kSphGroupMin holes, else one per kSphSlice holes, at least 2 and at most
-// max_group (>= 2: the resident workgroups of the device) and kSphMaxGroup.
-inline int sph_group(int64_t n0, int max_group)
-{
-    if (n0 <= kSphGroupMin) return 1;
-    const int64_t g = (n0 + kSphSlice - 1) / kSphSlice;
-    const int64_t cap = max_group < kSphMaxGroup ? max_group : kSphMaxGroup;
-    return (int)(g < cap ? g : cap);
-}
-
-// Shared state of an event's G workgroups (device memory, 256-byte aligned
-// pieces): the barrier counter, each workgroup's largest key, survivor count
-// and coordinate sums, the bin histograms of the slices (turned into each
-// slice's first position within every bin), the exclusive scan of the bin
-// totals within each workgroup's range of bins, and the totals of the ranges.
-struct SphGroupView {
-    uint32_t *bar;
-    double *gmax;        // [G]
-    double *sums;        // [G][3]
-    int32_t *kept;       // [G]
-    int32_t *range_tot;  // [G]
-    int32_t *colscan;    // [kSphBins]
-    int32_t *ghist;      // [G][kSphBins]
-};
-
-__host__ __device__ inline size_t sph_align(size_t v) { return (v + 255) & ~(size_t)255; }
-
-__host__ __device__ inline size_t sph_group_bytes(int G)
-{
-    return 256 + sph_align(8 * (size_t)G) + sph_align(24 * (size_t)G) + sph_align(4 * (size_t)G) +
-           sph_align(4 * (size_t)G) + sph_align(4 * (size_t)kSphBins) +
-           sph_align(4 * (size_t)kSphBins * G);
-}
-
-__host__ __device__ inline SphGroupView sph_group_view(char *p, int G)
-{
-    SphGroupView v;
-    size_t o = 0;
-    v.bar = reinterpret_cast<uint32_t *>(p + o);
-    o += 256;
-    v.gmax = reinterpret_cast<double *>(p + o);
-    o += sph_align(8 * (size_t)G);
-    v.sums = reinterpret_cast<double *>(p + o);
-    o += sph_align(24 * (size_t)G);
-    v.kept = reinterpret_cast<int32_t *>(p + o);
-    o += sph_align(4 * (size_t)G);
-    v.range_tot = reinterpret_cast<int32_t *>(p + o);
-    o += sph_align(4 * (size_t)G);
-    v.colscan = reinterpret_cast<int32_t *>(p + o);
-    o += sph_align(4 * (size_t)kSphBins);
-    v.ghist = reinterpret_cast<int32_t *>(p + o);
-    return v;
-}
-
 struct LaunchCfg {
     int kt;        // targets per thread
     int bs;        // block size = sources per LDS tile
@@ -221,7 +150,8 @@ hipError_t launch_summary(const DevBatch &bt, Sched *sc, hipStream_t s);
 // Simplified spherical model (Eq. 7): one workgroup per event of the list
 // dq.single (grid_single of them), then grid_shared resident workgroups
 // claiming the tickets of the shared events (one per workgroup of an event);
-// scratch holds 2 * n_total doubles.
+// scratch holds 2 * n_total doubles.  sph_occupancy: resident workgroups per
+// CU of the shared-event kernel.
 hipError_t launch_sph(const DevParams &dp, const DevBatch &bt, const DevQueue &dq, double *scratch,
                       int grid_single, int grid_shared, int64_t max_steps, int field_only,
                       double *field_out, hipStream_t s);

@@ -2,6 +2,7 @@
 // the repulsion field of the holes strictly closer to the event's centre,
 // with the carrier update and compaction of the brute-force path.
 #include "ct_device.hpp"
+#include "ct_sph_layout.hpp"
 
 namespace ct {
 
@@ -194,10 +195,10 @@ __device__ double sph_rank_large(const DevBatch &bt, const SphArgs &sa, int base
 // LDS of a workgroup of the spherical kernel.
 struct SphShared {
     int *hist;       // [kSphBins]
-    double *lkeys;   // [kSphLdsKeys]
+    double *lkeys;   // [kSphLdsKeys] (one workgroup per event only)
     int *wtot;       // [W]
     double *red;     // [W]
-    int *wcount;     // [kCompactChunks * W]
+    int *wcount;     // [kCompactChunks * W] (one workgroup per event), [W] (shared events)
     double *wsum;    // [4 * W]
     int *range_base; // [kSphMaxGroup]
     int *flag;
@@ -320,7 +321,7 @@ __device__ void block_sum4(double (&v)[4], double *red)
 __device__ void sph_event_group(const DevParams &dp, const DevBatch &bt, const SphArgs &sa,
                                 const SphGroupArgs &ga, int b, int g, int G, const SphShared &sh)
 {
-    constexpr int BS = kSphBlock, W = BS / 64;
+    constexpr int BS = kSphSharedBlock, W = BS / 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int base = bt.off[b];
     const uint32_t eid = (uint32_t)(bt.first_event_id + b);
@@ -356,14 +357,17 @@ __device__ void sph_event_group(const DevParams &dp, const DevBatch &bt, const S
             for (int q = tid; q < kSphBins; q += BS) st_dev(&gv.ghist[g * kSphBins + q], sh.hist[q]);
             if (!group_barrier(gv.bar, (uint32_t)G * ++nbar, ga, sh.flag)) return;
             for (int q = q0 + tid; q < q1; q += BS) {
-                int v[kSphMaxGroup];  // every slice's count first (independent loads), then the prefix
-#pragma unroll
-                for (int r = 0; r < kSphMaxGroup; ++r) v[r] = r < G ? gv.ghist[r * kSphBins + q] : 0;
+                // eight slices' counts at a time (independent loads), then their prefix
                 int run = 0;
+                for (int r0 = 0; r0 < G; r0 += 8) {
+                    int v[8];
 #pragma unroll
-                for (int r = 0; r < kSphMaxGroup; ++r) {
-                    if (r < G) st_dev(&gv.ghist[r * kSphBins + q], run);
-                    run += v[r];
+                    for (int r = 0; r < 8; ++r) v[r] = r0 + r < G ? gv.ghist[(r0 + r) * kSphBins + q] : 0;
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) {
+                        if (r0 + r < G) st_dev(&gv.ghist[(r0 + r) * kSphBins + q], run);
+                        run += v[r];
+                    }
                 }
                 sh.hist[q] = run;
             }
@@ -514,19 +518,6 @@ __device__ void sph_event_group(const DevParams &dp, const DevBatch &bt, const S
 // gets its own register allocation: k_sph_single takes every event of the
 // batch that one workgroup runs (one workgroup per such event, from the list
 // sa.single), k_sph_shared the events shared by several.
-#define CT_SPH_LDS                                                                             \
-    constexpr int W = kSphBlock / 64;                                                          \
-    static_assert(kSphBins % kSphBlock == 0, "bins per thread");                              \
-    __shared__ int hist[kSphBins];                                                             \
-    __shared__ double lkeys[kSphLdsKeys];                                                      \
-    __shared__ int wtot[W];                                                                    \
-    __shared__ double red[W];                                                                  \
-    __shared__ int s_wcount[kCompactChunks * W];                                               \
-    __shared__ double s_wsum[4 * W];                                                           \
-    __shared__ int s_range_base[kSphMaxGroup];                                                 \
-    __shared__ int s_flag;                                                                     \
-    const SphShared sh{hist, lkeys, wtot, red, s_wcount, s_wsum, s_range_base, &s_flag};
-
 __global__ __launch_bounds__(kSphBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void k_sph_single(DevParams dp, DevBatch bt, SphArgs sa)
 {
@@ -598,11 +589,21 @@ void k_sph_single(DevParams dp, DevBatch bt, SphArgs sa)
 // so every shared event but the last claimed one has all its workgroups
 // running; as long as the grid holds at least G workgroups, the missing ones
 // of the last event are claimed as soon as others finish.
-__global__ __launch_bounds__(kSphBlock) __attribute__((amdgpu_waves_per_eu(4)))
+// 1024 threads per workgroup (16 waves per CU) measured 14-20% faster than 512
+// on shared events, whose steps alternate short phases with barriers.
+__global__ __launch_bounds__(kSphSharedBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void k_sph_shared(DevParams dp, DevBatch bt, SphArgs sa, SphGroupArgs ga)
 {
-    CT_SPH_LDS
-    __shared__ int s_ticket;
+    constexpr int W = kSphSharedBlock / 64;
+    static_assert(kSphBins % kSphSharedBlock == 0, "bins per thread");
+    __shared__ int hist[kSphBins];
+    __shared__ int wtot[W];
+    __shared__ double red[W];
+    __shared__ int s_wcount[W];
+    __shared__ double s_wsum[4 * W];
+    __shared__ int s_range_base[kSphMaxGroup];
+    __shared__ int s_flag, s_ticket;
+    const SphShared sh{hist, nullptr, wtot, red, s_wcount, s_wsum, s_range_base, &s_flag};
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0)
@@ -621,7 +622,6 @@ void k_sph_shared(DevParams dp, DevBatch bt, SphArgs sa, SphGroupArgs ga)
         if (G > 1) sph_event_group(dp, bt, sa, ga, lo, t - ga.dq.tk_off[lo], G, sh);
     }
 }
-#undef CT_SPH_LDS
 
 // Ticket counter, error flag and the barrier counters of shared events,
 // cleared before a run.
@@ -652,22 +652,19 @@ hipError_t launch_sph(const DevParams &dp, const DevBatch &bt, const DevQueue &d
     if (grid_single > 0)
         hipLaunchKernelGGL(k_sph_single, dim3(grid_single), dim3(kSphBlock), 0, s, dp, bt, sa);
     if (grid_shared > 0)
-        hipLaunchKernelGGL(k_sph_shared, dim3(grid_shared), dim3(kSphBlock), 0, s, dp, bt, sa,
+        hipLaunchKernelGGL(k_sph_shared, dim3(grid_shared), dim3(kSphSharedBlock), 0, s, dp, bt, sa,
                            SphGroupArgs{dq, run_idle_ticks()});
     return hipGetLastError();
 }
 
-// Resident workgroups per CU of the spherical kernel (the smaller of the two
-// instantiations').
+// Resident workgroups per CU of the shared-event kernel.
 int sph_occupancy()
 {
-    int a = 0, b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, reinterpret_cast<const void *>(&k_sph_single),
-                                                     kSphBlock, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void *>(&k_sph_shared),
-                                                     kSphBlock, 0) != hipSuccess)
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_sph_shared),
+                                                     kSphSharedBlock, 0) != hipSuccess)
         return -1;
-    return a < b ? a : b;
+    return nb;
 }
 
 }  // namespace ct
