@@ -176,7 +176,8 @@ typedef struct {
     int32_t targets_per_thread;/* launch configuration in use */
     int32_t block_size;
     int32_t chunk_len;         /* source chunk length (ct_set_launch) */
-    int32_t workgroups;        /* resident workgroups of the step kernel */
+    int32_t workgroups;        /* workgroups of the step kernel (spherical model: one per
+                                  single-workgroup event plus those taking shared events) */
     uint64_t hole_steps;       /* sum over steps and events of N_a (carrier updates performed,
                                   both species) */
 } ct_run_stats;

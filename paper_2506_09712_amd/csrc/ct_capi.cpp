@@ -1005,7 +1005,7 @@ ct_status ct_collect(ct_ctx *c, int32_t *pixel_counts, double *xyz, int32_t *col
         r.targets_per_thread = spherical(c) ? 1 : c->cfg.kt;
         r.block_size = spherical(c) ? ct::kSphBlock : c->cfg.bs;
         r.chunk_len = spherical(c) ? 0 : c->cfg.chunk;
-        r.workgroups = c->grid;
+        r.workgroups = c->grid + (spherical(c) ? c->grid_shared : 0);
         *stats = r;
     }
     return CT_OK;
