@@ -26,15 +26,15 @@
  *    it (holes along the field, electrons against it), which makes like
  *    charges repel and opposite charges attract (Sec. 2.1 and its footnote).
  *  - Two species (optional, physics bit 3): besides its holes, an event
- *    simulates electrons (Sec. 2.1, "both electrons and holes are simulated
- *    as individual charge carriers").  Electron k of a cloud event starts at
+ *    simulates electrons (Sec. 2.1 follows every electron and every hole as
+ *    a carrier of its own).  Electron k of a cloud event starts at
  *    the position of hole k (the pair is created at one point).  Electrons
  *    drift away from the pixel plane with the Jacoboni-Canali electron laws,
  *    are collected at the entrance side (an update that leaves them at
  *    z >= H) and mirrored at the pixel plane (z -> -z); they are not counted
- *    in pixels.  An event ends when its last hole is collected (Algorithm 1:
- *    "until all holes reach the readout electrode"); electrons still
- *    drifting then keep their current position.
+ *    in pixels.  An event ends when its last hole is collected (Algorithm 1's
+ *    loop ends when every hole has reached the readout electrode); electrons
+ *    still drifting then keep their current position.
  *  - Simplified spherical model (optional, physics bit 4; Sec. 2.2, Eq. 7):
  *    the repulsion field at hole i is that of the holes strictly closer to
  *    the cloud centre c than i, as if concentrated at c:
