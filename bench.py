@@ -262,12 +262,24 @@ def main():
               file=sys.stderr, flush=True)
 
     if not a.no_cpu_baseline:
+        # endpoints of one more (untimed) run in each precision, for the error
+        # of the GPU results against the oracle on the events it simulates
+        gpu_runs = {}
+        for label, prec in (("fp32_batched", ct.CT_FP32), ("fp64_batched", ct.CT_FP64)):
+            with ct.Simulator(sensor, prec, device=0, launch=launch) as sim:
+                sim.seed(batch)
+                st_, _, _ = sim.step(0)
+                if st_ != 0:
+                    raise RuntimeError(f"{label} run did not finish: status {st_}")
+                gpu_runs[label] = sim.collect(carriers=True)
         import oracle
         oracle.build(force=False)
         cpairs, t2, k = 0, time.perf_counter(), 0
+        oracle_runs = []
         while k < batch.n_events and (time.perf_counter() - t2) < a.cpu_seconds:
             o = oracle.run(sensor, batch.event(k))
             cpairs += o["pairs"]
+            oracle_runs.append(o)
             k += 1
         cwall = time.perf_counter() - t2
         out["cpu_baseline"] = {"value": cpairs / cwall, "unit": "pair-interactions/s",
@@ -275,9 +287,38 @@ def main():
                                "sample": f"events 0..{k - 1} of {a.workload}, each simulated "
                                          f"to completion alone ({cpairs:.3e} pairs, {cwall:.1f} s)",
                                "events_per_s": k / cwall}
+        out["error_vs_oracle"] = error_vs_oracle(gpu_runs, oracle_runs)
         print(f"bench: oracle {cpairs / cwall:.3e} pairs/s on {oracle.threads()} threads",
               file=sys.stderr, flush=True)
+        e32, e64 = out["error_vs_oracle"]["fp32_batched"], out["error_vs_oracle"]["fp64_batched"]
+        print(f"bench: vs oracle on {k} events: FP32 endpoints max {e32['endpoint_um_max']:.2e} / "
+              f"p99 {e32['endpoint_um_p99']:.2e} / mean {e32['endpoint_um_mean']:.2e} um, pixel "
+              f"fractions max {e32['pixel_fraction_max_abs']:.2e}; FP64 endpoints max "
+              f"{e64['endpoint_um_max']:.2e} um", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
+
+
+def error_vs_oracle(gpu_runs, oracle_runs):
+    """Per precision: the (x, y) endpoint error of every carrier of the
+    oracle's events (max, 99th percentile, mean, um), the largest pixel charge
+    fraction error, and the share of carriers with the oracle's collection
+    step."""
+    res = {"events": len(oracle_runs)}
+    for label, g in gpu_runs.items():
+        off = g["offsets"]
+        d, frac, same, ncar = [], 0.0, 0, 0
+        for e, o in enumerate(oracle_runs):
+            sl = slice(int(off[e]), int(off[e + 1]))
+            d.append(np.hypot(*(g["xyz"][sl, :2] - o["xyz"][:, :2]).T))
+            n = max(int(o["pix"].sum()), 1)
+            frac = max(frac, float(np.abs(g["pix"][e] - o["pix"][0]).max()) / n)
+            same += int((g["cstep"][sl] == o["cstep"]).sum())
+            ncar += sl.stop - sl.start
+        d = np.concatenate(d) if d else np.zeros(1)
+        res[label] = {"endpoint_um_max": float(d.max()), "endpoint_um_p99": float(np.percentile(d, 99)),
+                      "endpoint_um_mean": float(d.mean()), "pixel_fraction_max_abs": frac,
+                      "collect_step_match": same / max(ncar, 1)}
+    return res
 
 
 def generator(a, ct, torch, kw):
