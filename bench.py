@@ -353,6 +353,9 @@ def generator(a, ct, torch, kw):
         carriers += int(info[:, 2].sum().item())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if not a.no_cpu_baseline:
+        ct.ct_generate(ctx, gen, n, 0, *ptrs)  # events 0.. again (untimed), for the oracle check
+        torch.cuda.synchronize()
     ct.ct_destroy(ctx)
     events_per_s = n * a.steps / wall
     achieved = OPS_PER_CARRIER * carriers / (kern_ms * 1e-3)
@@ -383,10 +386,17 @@ def generator(a, ct, torch, kw):
         import oracle.generator as og
         oracle.build(force=False)
         k, t2, chunk = 0, time.perf_counter(), 200
+        oc, oe = [], []
         while (time.perf_counter() - t2) < a.cpu_seconds and k < n:
-            og.generate(sensor, gen, chunk, first_event_id=k)
+            o = og.generate(sensor, gen, chunk, first_event_id=k)
+            oc.append(o["counts"])
+            oe.append(o["energy"])
             k += chunk
         cwall = time.perf_counter() - t2
+        gc, ge = counts[:k].cpu().numpy(), energy[:k].cpu().numpy()
+        out["error_vs_oracle"] = {
+            "events": k, "counts_equal": bool(np.array_equal(gc, np.concatenate(oc))),
+            "energy_kev_max_abs": float(np.abs(ge - np.concatenate(oe)).max())}
         out["cpu_baseline"] = {"value": k / cwall, "unit": "events/s", "cores": 1, "kind": "oracle",
                                "sample": f"events 0..{k - 1} of generator_25kev ({cwall:.1f} s), "
                                          f"the oracle's numpy generator on one thread"}
@@ -448,13 +458,21 @@ def spherical(a, ct, torch, sensor, batch, n_holes):
                      "avg_launch_ms": kern_ms / max(launches, 1), "launches": launches},
     }
     if not a.no_cpu_baseline:
+        with ct.Simulator(sensor, ct.CT_FP64, device=0) as sim:  # endpoints, untimed
+            sim.seed(batch)
+            sim.step(0)
+            gpu_run = sim.collect(carriers=True)
         import oracle
         oracle.build(force=False)
         ch, t2, k = 0, time.perf_counter(), 0
+        oracle_runs = []
         while k < batch.n_events and (time.perf_counter() - t2) < a.cpu_seconds:
-            ch += oracle.run(sensor, batch.event(k))["hole_steps"]
+            o = oracle.run(sensor, batch.event(k))
+            ch += o["hole_steps"]
+            oracle_runs.append(o)
             k += 1
         cwall = time.perf_counter() - t2
+        out["error_vs_oracle"] = error_vs_oracle({"fp64": gpu_run}, oracle_runs)
         out["cpu_baseline"] = {"value": k / cwall, "unit": "events/s", "cores": oracle.threads(),
                                "kind": "oracle",
                                "sample": f"events 0..{k - 1} of {a.workload}, spherical model, each "
