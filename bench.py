@@ -45,7 +45,12 @@ VALU_OP_PEAK = 256 * 64 * 2.4e9
 # edges of a 5-pixel row (24 compares and adds), the pixel index and the
 # histogram update (4)
 OPS_PER_CARRIER = 72
-FP32_VECTOR_PEAK = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 64 lanes x 2 x 2 x 2.4 GHz)
+FP32_VECTOR_PEAK = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 128 lanes x 2 (FMA) x 2.4 GHz)
+# Issue slots of one pair: 11 one-slot FP32 instructions and a v_rsq_f32 at a
+# quarter of their rate; at 128 lanes per CU per clock and 2.4 GHz that bounds
+# the pair loop at 256 * 128 * 2.4e9 / 15 pairs/s.
+SLOTS_PER_PAIR = 15
+PAIR_SLOT_BOUND = 256 * 128 * 2.4e9 / SLOTS_PER_PAIR
 HBM_PEAK = 8.0e12             # MI355X HBM3E bytes/s
 FLOP_PER_PAIR = 20            # N-body convention for one softened pair interaction
 
@@ -225,7 +230,9 @@ def main():
                      "hole_steps_per_launch": hsteps / max(launches, 1),
                      "kernel": f"k_run_f32<{st.targets_per_thread},{st.block_size}>",
                      "avg_launch_ms": kern_ms / max(launches, 1),
-                     "launches": launches, "flop_per_pair": FLOP_PER_PAIR},
+                     "launches": launches, "flop_per_pair": FLOP_PER_PAIR,
+                     "slots_per_pair": SLOTS_PER_PAIR,
+                     "frac_of_issue_bound": (pairs / (kern_ms * 1e-3)) / PAIR_SLOT_BOUND if kern_ms > 0 else None},
     }
 
     if not a.no_plain:
