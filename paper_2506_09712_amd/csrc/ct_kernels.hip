@@ -265,15 +265,27 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
                     const int a0 = seg == 0 ? sb : max(sb, nh);
                     const int a1 = seg == 0 ? min(se, nh) : se;
                     const double sgn = seg == 0 ? 1.0 : -1.0;
+                    // the next tile's source is loaded into registers while the
+                    // current tile is computed
+                    double px = 0.0, py = 0.0, pz = 0.0;
+                    if (a0 + tid < a1) {
+                        px = bt.cx[base + a0 + tid];
+                        py = bt.cy[base + a0 + tid];
+                        pz = bt.cz[base + a0 + tid];
+                    }
                     for (int s0 = a0; s0 < a1; s0 += BS) {
                         __syncthreads();
                         const int j = s0 + tid;
                         float4 v = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
-                        if (j < a1)
-                            v = make_float4((float)(bt.cx[base + j] - rx), (float)(bt.cy[base + j] - ry),
-                                            (float)(bt.cz[base + j] - rz), 0.0f);
+                        if (j < a1) v = make_float4((float)(px - rx), (float)(py - ry), (float)(pz - rz), 0.0f);
                         tile[tid] = v;
                         __syncthreads();
+                        const int jn = j + BS;
+                        if (jn < a1) {
+                            px = bt.cx[base + jn];
+                            py = bt.cy[base + jn];
+                            pz = bt.cz[base + jn];
+                        }
                         if (!wave_has_targets) continue;
                         const int cnt = (min(BS, a1 - s0) + CT_PAIR_UNROLL - 1) / CT_PAIR_UNROLL * CT_PAIR_UNROLL;
                         float ax[KT], ay[KT], az[KT];
