@@ -50,7 +50,13 @@ FP32_VECTOR_PEAK = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 128 lanes x 
 # quarter of their rate; at 128 lanes per CU per clock and 2.4 GHz that bounds
 # the pair loop at 256 * 128 * 2.4e9 / 15 pairs/s.
 SLOTS_PER_PAIR = 15
-PAIR_SLOT_BOUND = 256 * 128 * 2.4e9 / SLOTS_PER_PAIR
+# The Newton-pair kernel takes each unordered pair once for both holes: 3 sub,
+# 3 FMA, v_rsq (4 slots), 2 mul, 3 + 3 FMA and 3 DPP lane moves = 21 slots
+# for two ordered pairs (a tile with itself still costs 15 per ordered pair).
+# Executed FLOP: 24 per unordered pair (FMA as 2, rsqrt as 1), 12 per ordered.
+NEWTON_SLOTS_PER_PAIR = 10.5
+NEWTON_EXECUTED_FLOP_PER_PAIR = 12
+ISSUE_SLOTS_PER_S = 256 * 128 * 2.4e9
 HBM_PEAK = 8.0e12             # MI355X HBM3E bytes/s
 FLOP_PER_PAIR = 20            # N-body convention for one softened pair interaction
 
@@ -92,7 +98,7 @@ KERNEL_SOURCES = {
     "generator": ("ct_gen.hip", "ct_device.hpp", "ct_internal.hpp"),
 }
 TRAFFIC_PROFILES = {
-    "pairs": os.path.join(ROOT, "profiles", "k_run_f32_batch_8kev_traffic.md"),
+    "pairs": os.path.join(ROOT, "profiles", "k_run_newton_batch_8kev_traffic.md"),
     "spherical": os.path.join(ROOT, "profiles", "k_sph_batch_8kev_traffic.md"),
     "generator": os.path.join(ROOT, "profiles", "k_gen_generator_25kev_traffic.md"),
 }
@@ -173,9 +179,9 @@ def main():
         return spherical(a, ct, torch, sensor, batch, n_holes)
     tune = ct.CT_OPT_AUTOTUNE if (a.autotune and not launch) else 0
 
-    def timed_runs(label):
+    def timed_runs(label, extra=0):
         # HIP events around the one step-kernel run of each ct_step call
-        sim = ct.Simulator(sensor, ct.CT_FP32, device=0, options=ct.CT_OPT_TIMING | tune,
+        sim = ct.Simulator(sensor, ct.CT_FP32, device=0, options=ct.CT_OPT_TIMING | tune | extra,
                            launch=launch)
         for _ in range(a.warmup):
             simulate(ct, sim, batch)
@@ -201,6 +207,10 @@ def main():
     events_per_s = batch.n_events * a.steps / wall
     traffic, traffic_note = measured_traffic("pairs", hsteps / max(launches, 1))
     achieved = FLOP_PER_PAIR * pairs / (kern_ms * 1e-3) if kern_ms > 0 else None
+    newton = bool(st.newton_pairs)
+    slots = NEWTON_SLOTS_PER_PAIR if newton else SLOTS_PER_PAIR
+    executed = (NEWTON_EXECUTED_FLOP_PER_PAIR if newton else FLOP_PER_PAIR) * pairs / (kern_ms * 1e-3) \
+        if kern_ms > 0 else None
     print(f"bench: step kernel {kern_ms / max(launches, 1):.3f} ms avg over {launches} launches, "
           f"{achieved / 1e12 if achieved else 0:.1f} TFLOP/s", file=sys.stderr, flush=True)
 
@@ -228,11 +238,17 @@ def main():
                      "traffic": traffic, "traffic_note": traffic_note,
                      "algorithmic_bytes_per_launch": ALG_BYTES_PER_HOLE_STEP * hsteps / max(launches, 1),
                      "hole_steps_per_launch": hsteps / max(launches, 1),
-                     "kernel": f"k_run_f32<{st.targets_per_thread},{st.block_size}>",
+                     "kernel": "k_run_newton<256>" if newton else
+                               f"k_run_f32<{st.targets_per_thread},{st.block_size}>",
+                     "pair_evaluation": "each unordered pair once, applied to both holes" if newton
+                                        else "every ordered pair",
                      "avg_launch_ms": kern_ms / max(launches, 1),
                      "launches": launches, "flop_per_pair": FLOP_PER_PAIR,
-                     "slots_per_pair": SLOTS_PER_PAIR,
-                     "frac_of_issue_bound": (pairs / (kern_ms * 1e-3)) / PAIR_SLOT_BOUND if kern_ms > 0 else None},
+                     "executed_tflops": executed / 1e12 if executed else None,
+                     "executed_frac": executed / FP32_VECTOR_PEAK if executed else None,
+                     "slots_per_pair": slots,
+                     "frac_of_issue_bound": (pairs / (kern_ms * 1e-3)) / (ISSUE_SLOTS_PER_S / slots)
+                     if kern_ms > 0 else None},
     }
 
     if not a.no_plain:
@@ -265,6 +281,9 @@ def main():
         out["ablation"] = {"fp32_batched": value, "fp64_batched": b64, "fp32_plain": p32,
                            "fp64_plain": p64, "unit": "pair-interactions/s",
                            "plain_events": n_plain}
+        if newton:
+            p1, w1 = timed_runs("fp32-batched, every ordered pair", ct.CT_OPT_ONE_SIDED)[:2]
+            out["ablation"]["fp32_batched_one_sided"] = p1 / w1
         print(f"bench: fp64-plain {p64:.3e}, fp64-batched {b64:.3e}, fp32-plain {p32:.3e} pairs/s",
               file=sys.stderr, flush=True)
 

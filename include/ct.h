@@ -104,10 +104,15 @@ enum { CT_REPULSION = 1u, CT_DRIFT = 2u, CT_DIFFUSION = 4u, CT_ELECTRONS = 8u, C
 /* options bits */
 enum {
     CT_OPT_TIMING = 1u,   /* time every run of the step kernel with HIP events (ct_run_stats) */
-    CT_OPT_AUTOTUNE = 4u  /* on seeding, time the launch configurations on one field evaluation
+    CT_OPT_AUTOTUNE = 4u, /* on seeding, time the launch configurations on one field evaluation
                              of the seeded state and keep the fastest (cached per precision and
                              batch-shape bucket); the chosen configuration sets the grouping of
                              the field sum (see ct_set_launch) */
+    CT_OPT_ONE_SIDED = 8u /* CT_FP32: evaluate every ordered pair (i, j) on its own.  By default
+                             a hole-only FP32 run with one target per thread and blocks of 256
+                             evaluates each unordered pair once and applies it to both holes
+                             (Eq. 4 is antisymmetric), in events of up to 131072 drifting holes;
+                             the two differ only in FP32 rounding */
 };
 
 typedef struct {
@@ -180,6 +185,9 @@ typedef struct {
                                   single-workgroup event plus those taking shared events) */
     uint64_t hole_steps;       /* sum over steps and events of N_a (carrier updates performed,
                                   both species) */
+    int32_t newton_pairs;      /* 1: the FP32 field evaluates each unordered pair once and applies
+                                  it to both holes (CT_OPT_ONE_SIDED not set; see there) */
+    int32_t reserved;
 } ct_run_stats;
 
 /* Create a context for one sensor configuration on one gfx950 device.

@@ -8,7 +8,8 @@ include/ct.h; this package holds the kernels' sources (csrc/), the in-tree
 build (build.py) and the ctypes binding (binding.py).
 """
 from .binding import (  # noqa: F401
-    CT_DIFFUSION, CT_DRIFT, CT_ELECTRONS, CT_FP32, CT_FP64, CT_OPT_AUTOTUNE, CT_OPT_TIMING,
+    CT_DIFFUSION, CT_DRIFT, CT_ELECTRONS, CT_FP32, CT_FP64, CT_OPT_AUTOTUNE, CT_OPT_ONE_SIDED,
+    CT_OPT_TIMING,
     CT_REPULSION, CT_SPHERICAL, CtError, EXPORTS, ct_generate, generate, make_gen_params,
     Simulator, ct_bind_workspace, ct_collect, ct_destroy, ct_event_carriers, ct_field,
     ct_init_sensor, ct_philox, ct_seed_events, ct_set_launch, ct_step, ct_workspace_bytes, load,

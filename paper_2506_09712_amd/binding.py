@@ -34,6 +34,7 @@ CT_MOB_JACOBONI, CT_MOB_CONSTANT = 0, 1
 CT_REPULSION, CT_DRIFT, CT_DIFFUSION, CT_ELECTRONS, CT_SPHERICAL = 1, 2, 4, 8, 16
 CT_OPT_TIMING = 1
 CT_OPT_AUTOTUNE = 4
+CT_OPT_ONE_SIDED = 8
 
 _STATUS = {0: "CT_OK", -1: "CT_EINVAL", -2: "CT_ESTATE", -3: "CT_ENOMEM", -4: "CT_EDEVICE",
            -5: "CT_EMAXSTEPS", -6: "CT_ENONFINITE"}
@@ -81,6 +82,7 @@ class ct_run_stats(C.Structure):
         ("field_launches", C.c_int64), ("field_kernel_ms", C.c_double), ("step_wall_ms", C.c_double),
         ("targets_per_thread", C.c_int32), ("block_size", C.c_int32), ("chunk_len", C.c_int32),
         ("workgroups", C.c_int32), ("hole_steps", C.c_uint64),
+        ("newton_pairs", C.c_int32), ("reserved", C.c_int32),
     ]
 
 

@@ -103,7 +103,7 @@ ct_status check_params(const ct_sensor_params *p)
     if ((p->physics_flags & CT_DRIFT) && !(p->v_bias > p->v_dep && p->v_dep >= 0.0))
         return fail(CT_EINVAL, "the linear drift field needs 0 <= v_dep < v_bias (Eq. 6)");
     if (p->max_steps <= 0) return fail(CT_EINVAL, "max_steps must be > 0");
-    if (p->options & ~(uint32_t)(CT_OPT_TIMING | CT_OPT_AUTOTUNE))
+    if (p->options & ~(uint32_t)(CT_OPT_TIMING | CT_OPT_AUTOTUNE | CT_OPT_ONE_SIDED))
         return fail(CT_EINVAL, "unknown option bits 0x%x", p->options);
     double mu0, ec, beta;
     hole_mobility_params(*p, mu0, ec, beta);
@@ -309,9 +309,21 @@ QueueLayout make_queue_layout(const BatchShape &s, const ct::LaunchCfg &cfg, boo
         int64_t chunks = 1;
         if (repulsion && n0 > 0 && !spherical)
             chunks = std::min<int64_t>((n0 + cfg.chunk - 1) / cfg.chunk, ct::kMaxChunks);
+        int64_t slots = chunks > 1 ? chunks : 0;
+        int64_t ev_items = tiles * chunks;
+        if (cfg.newton && n0 > 0) {
+            // slots and items grow with the hole count within each of the two
+            // splits: bound both at the largest count that takes each
+            const int ct_ = cfg.chunk / ct::kSymTile;
+            const int n_sym = (int)std::min<int64_t>(n0, (int64_t)ct::kSymMaxTiles * ct::kSymTile);
+            const ct::SymSplit a = ct::sym_split(n_sym, ct_);
+            const ct::SymSplit z = ct::sym_split((int)n0, ct_);
+            slots = std::max<int64_t>(ct::sym_slots(a), z.newton ? 0 : chunks);
+            ev_items = std::max<int64_t>((int64_t)a.T * a.R, z.newton ? 0 : tiles * chunks);
+        }
         Q.tile_base_h[b + 1] = Q.tile_base_h[b] + (int32_t)tiles;
-        Q.part_off_h[b + 1] = Q.part_off_h[b] + (chunks > 1 ? 3 * n0 * chunks : 0);
-        items += tiles * chunks;
+        Q.part_off_h[b + 1] = Q.part_off_h[b] + 3 * n0 * slots;
+        items += ev_items;
     }
     Q.tk_off_h.assign(s.B + 1, 0);
     Q.grp_off_h.assign(s.B + 1, 0);
@@ -443,8 +455,22 @@ ct_status set_device(ct_ctx *c)
 // Work queue of the seeded batch for cfg, and the resident grid.  The queue
 // memory is kept while it is large enough; its sequence words are cleared
 // whenever it is (re)allocated, so no stale ticket can match a generation.
-ct_status prepare_queue(ct_ctx *c, const ct::LaunchCfg &cfg)
+// The launch configuration with the Newton-pair kernel switched on where it
+// applies: FP32 repulsion among holes only, one target per thread, blocks
+// of kSymTile, at most kSymMaxC tiles per chunk.
+ct::LaunchCfg resolve_cfg(const ct_ctx *c, ct::LaunchCfg cfg)
 {
+    const uint32_t f = c->p.physics_flags;
+    cfg.newton = c->p.precision == CT_FP32 && (f & CT_REPULSION) && !(f & CT_ELECTRONS) &&
+                 !(f & CT_SPHERICAL) && !(c->p.options & CT_OPT_ONE_SIDED) && cfg.kt == 1 &&
+                 cfg.bs == ct::kSymTile && cfg.chunk % ct::kSymTile == 0 &&
+                 cfg.chunk / ct::kSymTile <= ct::kSymMaxC;
+    return cfg;
+}
+
+ct_status prepare_queue(ct_ctx *c, const ct::LaunchCfg &cfg_in)
+{
+    const ct::LaunchCfg cfg = resolve_cfg(c, cfg_in);
     const bool repulsion = (c->p.physics_flags & CT_REPULSION) != 0;
     const bool spherical = (c->p.physics_flags & CT_SPHERICAL) != 0;
     int sph_cap = 0;
@@ -520,9 +546,10 @@ ct_status prepare_queue(ct_ctx *c, const ct::LaunchCfg &cfg)
 // One run of the persistent kernel: queue the first step of every eligible
 // event, run until every event is finished or parked, then read back the
 // control block (and the drifting-hole count and steps taken).
-ct_status run_once(ct_ctx *c, const ct::LaunchCfg &cfg, int64_t max_steps, int field_only,
+ct_status run_once(ct_ctx *c, const ct::LaunchCfg &cfg_in, int64_t max_steps, int field_only,
                    double *field_out, bool timing)
 {
+    const ct::LaunchCfg cfg = resolve_cfg(c, cfg_in);
     if (++c->gen == 0) ++c->gen;  // 0 is the cleared state of a sequence word
     c->dq.gen = c->gen;
     const int fp32 = c->p.precision == CT_FP32;
@@ -647,7 +674,7 @@ ct_status autotune(ct_ctx *c)
         // long chunks suit large batches (fewer partial fields), short chunks
         // and small tiles suit a few events (more work items per step)
         const std::vector<ct::LaunchCfg> cand = {
-            {1, 256, 512},  {1, 256, 768},  {1, 256, 1280}, {1, 256, 1536},
+            {1, 256, 256},  {1, 256, 512},  {1, 256, 768},  {1, 256, 1280}, {1, 256, 1536},
             {1, 256, 2304}, {1, 128, 256},  {1, 128, 512},  {2, 256, 1280}};
         float best_ms = 1e30f;
         const double ms0 = c->field_ms;
@@ -1006,6 +1033,7 @@ ct_status ct_collect(ct_ctx *c, int32_t *pixel_counts, double *xyz, int32_t *col
         r.block_size = spherical(c) ? ct::kSphBlock : c->cfg.bs;
         r.chunk_len = spherical(c) ? 0 : c->cfg.chunk;
         r.workgroups = c->grid + (spherical(c) ? c->grid_shared : 0);
+        r.newton_pairs = resolve_cfg(c, c->cfg).newton;
         *stats = r;
     }
     return CT_OK;

@@ -121,6 +121,7 @@ struct LaunchCfg {
     int kt;        // targets per thread
     int bs;        // block size = sources per LDS tile
     int chunk;     // source chunk length (a multiple of bs; events longer than this are split)
+    int newton;    // 1: FP32 pair kernel that takes each unordered pair once (kt 1, bs 256)
 };
 
 // Parameters of the event generator (Sec. 4.2), precomputed on the host.
@@ -168,6 +169,75 @@ hipError_t launch_scatter_alive(const DevBatch &bt, int n_max, hipStream_t s);
 hipError_t launch_philox(const DevParams &dp, const uint32_t *ctr, int64_t n, uint32_t *words,
                          double *normals, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+
+// Newton-pair split of the FP32 field (Eq. 4 is antisymmetric: the term of
+// pair (i, j) is minus that of (j, i), so one evaluation serves both holes).
+// An event of n holes has T tiles of kSymTile.  Tile a meets the tiles
+// a + o (mod T) for the offsets o in [0, P_a): offset 0 is the tile with
+// itself (every ordered pair evaluated), the others are Newton pairs whose
+// reaction goes to the partner tile.  With P_a = (T - 1) / 2 + 1, plus one
+// for a < T / 2 when T is even, every unordered pair of tiles is met exactly
+// once.  An item takes C consecutive offsets of one tile (R items per tile).
+// Events of more than kSymMaxTiles tiles (whose reaction partials would need
+// too much memory) evaluate every ordered pair: item r of a tile takes the
+// tiles [r C, r C + C) as sources, C lengthened so that R <= kMaxChunks.
+// Partial fields: slot r holds the target side of item r of each tile, slot
+// R + o - 1 the reaction a tile receives through offset o.  Everything
+// depends on n and C alone.
+constexpr int kSymTile = 256;
+constexpr int kSymMaxTiles = 512;
+constexpr int kSymMaxC = 15;  // longest chunk, in tiles
+
+struct SymSplit {
+    int T;        // tiles
+    int C;        // offsets (partner tiles) per item
+    int R;        // items per tile
+    int P;        // largest partner count (Newton pairs), or T
+    int newton;   // 1: Newton pairs
+};
+
+__host__ __device__ inline SymSplit sym_split(int n, int chunk_tiles)
+{
+    SymSplit s;
+    s.T = (n + kSymTile - 1) / kSymTile;
+    s.newton = s.T <= kSymMaxTiles;
+    if (s.newton) {
+        s.P = s.T / 2 + 1;
+        s.C = chunk_tiles;
+    } else {
+        s.P = s.T;
+        const int c_min = (s.T + kMaxChunks - 1) / kMaxChunks;
+        s.C = chunk_tiles > c_min ? chunk_tiles : c_min;
+    }
+    s.R = s.T > 0 ? (s.P + s.C - 1) / s.C : 0;
+    return s;
+}
+
+// Partner offsets of tile a: [0, sym_partners(T, a)).
+__host__ __device__ inline int sym_partners(int T, int a)
+{
+    return (T - 1) / 2 + 1 + ((T % 2 == 0 && a < T / 2) ? 1 : 0);
+}
+
+// Reactions tile b receives: through the offsets [1, sym_received(T, b)].
+__host__ __device__ inline int sym_received(int T, int b)
+{
+    return T % 2 == 1 ? (T - 1) / 2 : T / 2 - 1 + (b >= T / 2 ? 1 : 0);
+}
+
+// Contributions a tile waits for, and whether partial fields are used at all.
+__host__ __device__ inline int sym_expected(const SymSplit &s, int b)
+{
+    return s.R + (s.newton ? sym_received(s.T, b) : 0);
+}
+__host__ __device__ inline bool sym_partials(const SymSplit &s)
+{
+    return s.newton ? s.T > 1 : s.R > 1;
+}
+__host__ __device__ inline int sym_slots(const SymSplit &s)
+{
+    return sym_partials(s) ? (s.newton ? s.R + s.P - 1 : s.R) : 0;
+}
 
 // Source chunk length and count of an event of n drifting holes: chunks of
 // `chunk` sources (a multiple of bs), lengthened to whole tiles so that no

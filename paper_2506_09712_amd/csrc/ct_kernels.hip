@@ -448,6 +448,278 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
     }
 }
 
+// ------------------------------------------------- Newton pairs (FP32, holes)
+
+// Lane l receives the value of lane l + 1 (mod 64): DPP wave rotate.
+__device__ __forceinline__ float lane_up(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x134,
+                                                              0xF, 0xF, true));
+}
+
+// A wave's 64 targets against one block of 64 sources, staged twice in a row
+// (x y z of entries 0..127).  With REACT, lane l meets source (l + s) mod 64
+// at step s, so each (target, source) pair of the block is met once, and the
+// lane carries that source's reaction (minus the pair term, Eq. 4
+// antisymmetry) in b, which moves one lane down after each step: after 64
+// steps every lane holds the reaction on its own source.  Without REACT all
+// lanes meet source s at step s (broadcast reads) and b is untouched.
+template <bool REACT>
+__device__ __forceinline__ void sweep64(const float *__restrict__ p, float s2, float tx, float ty,
+                                        float tz, float &ax, float &ay, float &az, float &bx,
+                                        float &by, float &bz)
+{
+    for (int s0 = 0; s0 < 64; s0 += CT_PAIR_UNROLL) {
+#pragma unroll
+        for (int u = 0; u < CT_PAIR_UNROLL; ++u) {
+            const float *q = p + 3 * (s0 + u);
+            const float dx = tx - q[0];
+            const float dy = ty - q[1];
+            const float dz = tz - q[2];
+            float r2 = fmaf(dx, dx, s2);
+            r2 = fmaf(dy, dy, r2);
+            r2 = fmaf(dz, dz, r2);
+            const float inv = __builtin_amdgcn_rsqf(r2);
+            const float inv3 = inv * inv * inv;
+            ax = fmaf(dx, inv3, ax);
+            ay = fmaf(dy, inv3, ay);
+            az = fmaf(dz, inv3, az);
+            if constexpr (REACT) {
+                bx = lane_up(fmaf(-dx, inv3, bx));
+                by = lane_up(fmaf(-dy, inv3, by));
+                bz = lane_up(fmaf(-dz, inv3, bz));
+            }
+        }
+    }
+}
+
+// Most tiles one item contributes to: its own and one partner per offset.
+constexpr int kMaxTouch = kSymMaxC + 1;
+
+// The persistent loop with the Newton-pair split of the field (events of
+// holes only, FP32, one target per thread, tiles of kSymTile; the split is
+// described with sym_split).  An item stages each partner tile in LDS as
+// four doubled blocks of 64; every wave sweeps its 64 targets over them.
+// The reactions of the four waves are summed per source in wave order (FP64)
+// into the partner's partial slot; the target side folds each partner
+// tile's FP32 sum into FP64 and goes to the item's own slot.  Each item then
+// counts down the tiles it contributed to; the workgroup that completes a
+// tile sums its slots in slot order and updates it, and the one that
+// completes the event's last tile compacts the event and queues its next
+// step, as in run_loop.
+template <int BS>
+__device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const DevQueue &dq,
+                                const RunArgs &ra, float *src, float *react)
+{
+    static_assert(BS == kSymTile, "one target per thread over tiles of kSymTile");
+    constexpr int W = BS / 64;
+    __shared__ QItem s_item;
+    __shared__ int s_go;
+    __shared__ int s_wcount[kCompactChunks * W];
+    __shared__ double s_wsum[3 * W];
+    __shared__ int s_items, s_kept;
+    __shared__ uint32_t s_t0;
+    __shared__ int s_fin[kMaxTouch];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    Sched *sc = dq.sc;
+    const uint32_t n_events = (uint32_t)bt.n_events;
+    const int ctiles = ra.chunk / BS;
+
+    for (;;) {
+        __syncthreads();  // LDS of the previous item is free
+        if (tid == 0) {
+            QItem it{};
+            s_go = claim(dq, n_events, ra.idle_ticks, it);
+            s_item = it;
+        }
+        __syncthreads();
+        if (!s_go) break;
+        const QItem it = s_item;
+        const int b = it.e, n = it.n, a = it.tile, r = it.chunk;
+        const int base = bt.off[b];
+        const int n0 = bt.off[b + 1] - base;
+        set_item_priority(bt.ref[4 * b + 2], dp.H);
+        const SymSplit sp = sym_split(n, ctiles);
+        const double rx = bt.ref[4 * b + 0], ry = bt.ref[4 * b + 1], rz = bt.ref[4 * b + 2];
+        const int64_t po = dq.part_off[b];
+        // targets past the end are parked far away, where every pair term
+        // with them underflows to 0 (they also act as sources here)
+        const int si = a * BS + tid;
+        float tx = 1e18f, ty = 1e18f, tz = 1e18f;
+        if (si < n) {
+            tx = (float)(bt.cx[base + si] - rx);
+            ty = (float)(bt.cy[base + si] - ry);
+            tz = (float)(bt.cz[base + si] - rz);
+        }
+        const bool wave_has_targets = a * BS + w * 64 < n;
+        const int o0 = r * sp.C;
+        const int o1 = min(o0 + sp.C, sp.newton ? sym_partners(sp.T, a) : sp.T);
+        double ex = 0.0, ey = 0.0, ez = 0.0;
+        for (int o = o0; o < o1; ++o) {
+            const int pt = sp.newton ? (a + o) % sp.T : o;  // partner tile
+            const bool reacts = sp.newton && o > 0;
+            const int sj = pt * BS + tid;
+            float px = 1e18f, py = 1e18f, pz = 1e18f;
+            if (sj < n) {
+                px = (float)(bt.cx[base + sj] - rx);
+                py = (float)(bt.cy[base + sj] - ry);
+                pz = (float)(bt.cz[base + sj] - rz);
+            }
+            __syncthreads();  // the previous partner's sources and reactions are consumed
+            float *d = src + 3 * (w * 128 + lane);
+            d[0] = px;
+            d[1] = py;
+            d[2] = pz;
+            d[192] = px;
+            d[193] = py;
+            d[194] = pz;
+            __syncthreads();
+            const int nblk = min(W, (n - pt * BS + 63) / 64);  // blocks holding holes
+            float ax = 0.0f, ay = 0.0f, az = 0.0f;
+            if (reacts) {
+                for (int v = 0; v < W; ++v) {
+                    float bx = 0.0f, by = 0.0f, bz = 0.0f;
+                    if (wave_has_targets && v < nblk)
+                        sweep64<true>(src + 3 * (v * 128 + lane), dp.s2f, tx, ty, tz, ax, ay, az,
+                                      bx, by, bz);
+                    float *q = react + 3 * (w * BS + v * 64 + lane);
+                    q[0] = bx;
+                    q[1] = by;
+                    q[2] = bz;
+                }
+                __syncthreads();
+                if (sj < n) {
+                    double qx = 0.0, qy = 0.0, qz = 0.0;
+#pragma unroll
+                    for (int w2 = 0; w2 < W; ++w2) {
+                        const float *q = react + 3 * (w2 * BS + tid);
+                        qx += (double)q[0];
+                        qy += (double)q[1];
+                        qz += (double)q[2];
+                    }
+                    const int64_t o2 = po + 3 * (int64_t)(sp.R + o - 1) * n0 + sj;
+                    st_dev(&dq.part[o2], qx);
+                    st_dev(&dq.part[o2 + n0], qy);
+                    st_dev(&dq.part[o2 + 2 * n0], qz);
+                }
+            } else if (wave_has_targets) {
+                float bx = 0.0f, by = 0.0f, bz = 0.0f;
+                for (int v = 0; v < nblk; ++v)
+                    sweep64<false>(src + 3 * v * 128, dp.s2f, tx, ty, tz, ax, ay, az, bx, by, bz);
+            }
+            ex += (double)ax;
+            ey += (double)ay;
+            ez += (double)az;
+        }
+
+        // the rest of the item holds up every later step of its event
+        __builtin_amdgcn_s_setprio(3);
+        const bool split = sym_partials(sp);
+        const int oa = max(o0, 1);
+        const int ntouch = split ? 1 + (sp.newton ? max(0, o1 - oa) : 0) : 1;
+        if (split) {
+            if (si < n) {
+                const int64_t o2 = po + 3 * (int64_t)r * n0 + si;
+                st_dev(&dq.part[o2], ex);
+                st_dev(&dq.part[o2 + n0], ey);
+                st_dev(&dq.part[o2 + 2 * n0], ez);
+            }
+            wait_own_stores();
+            __syncthreads();
+            if (tid < ntouch) {
+                const int u = tid == 0 ? a : (a + oa + tid - 1) % sp.T;
+                s_fin[tid] = dec_is_last(&dq.chunks_left[dq.tile_base[b] + u]) ? u : -1;
+            }
+        } else if (tid == 0) {
+            s_fin[0] = a;
+        }
+        __syncthreads();
+        for (int k = 0; k < ntouch; ++k) {
+            const int u = s_fin[k];
+            if (u < 0) continue;
+            const int s = u * BS + tid;
+            if (s < n) {
+                double fx = ex, fy = ey, fz = ez;
+                if (split) {
+                    // own slots in item order, then reactions by offset
+                    const int nslot = sym_expected(sp, u);
+                    fx = fy = fz = 0.0;
+                    for (int k2 = 0; k2 < nslot; ++k2) {
+                        const int64_t o2 = po + 3 * (int64_t)k2 * n0 + s;
+                        fx += dq.part[o2];
+                        fy += dq.part[o2 + n0];
+                        fz += dq.part[o2 + 2 * n0];
+                    }
+                }
+                field_or_advance(dp, bt, b, base + s, dp.K * fx, dp.K * fy, dp.K * fz,
+                                 ra.field_only, ra.field_out);
+            }
+            wait_own_stores();
+            __syncthreads();
+            if (tid == 0) s_go = dec_is_last(&dq.tiles_left[b * kEventLine]);
+            __syncthreads();
+            if (!s_go) continue;
+
+            // every tile of the event's step is updated
+            if (ra.field_only) {
+                if (tid == 0) add_relaxed(&sc->done.v, 1u);
+                break;
+            }
+            int holes_kept = 0;
+            const int kept = compact_event<BS>(bt, b, n, n, dp.H, 1, s_wcount, s_wsum, holes_kept);
+            if (tid == 0) {
+                int items = 0;
+                uint32_t t0q = 0;
+                if (holes_kept > 0 && bt.call_steps[b] < ra.max_steps) {
+                    const SymSplit s2 = sym_split(kept, ctiles);
+                    items = s2.T * s2.R;
+                    t0q = add_relaxed(&sc->tail.v, (uint32_t)items);
+                    if ((uint64_t)t0q + (uint64_t)items > (uint64_t)dq.cap) {
+                        st_relaxed(&sc->exhausted.v, 1u);  // parked; the host runs again
+                        items = 0;
+                    }
+                }
+                if (items == 0) add_relaxed(&sc->done.v, 1u);
+                s_items = items;
+                s_kept = kept;
+                s_t0 = t0q;
+            }
+            __syncthreads();
+            const int items = s_items;
+            if (items > 0) {
+                const SymSplit s2 = sym_split(s_kept, ctiles);
+                const uint32_t t0q = s_t0;
+                const int tb = dq.tile_base[b];
+                for (int j = tid; j < s2.T; j += BS) st_dev(&dq.chunks_left[tb + j], sym_expected(s2, j));
+                if (tid == 0) st_dev(&dq.tiles_left[b * kEventLine], s2.T);
+                for (int i = tid; i < items; i += BS) {
+                    int32_t *q = reinterpret_cast<int32_t *>(dq.q + t0q + i);
+                    st_dev(q, b);
+                    st_dev(q + 1, i / s2.R);
+                    st_dev(q + 2, i % s2.R);
+                    st_dev(q + 3, s_kept);
+                    st_dev(q + 4, s_kept);
+                }
+                wait_own_stores();
+                __syncthreads();
+                if (tid == 0) fence_release();
+                __syncthreads();  // the write-back has completed before any sequence word is set
+                for (int i = tid; i < items; i += BS) st_relaxed(&dq.seq[t0q + i], dq.gen);
+            }
+            break;  // only one tile is the event's last
+        }
+    }
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(CT_F32_WAVES_PER_EU)))
+void k_run_newton(DevParams dp, DevBatch bt, DevQueue dq, RunArgs ra)
+{
+    __shared__ float src[3 * 2 * BS];             // four blocks of 64 sources, each twice
+    __shared__ float react[3 * BS * (BS / 64)];   // reactions per wave and source
+    run_loop_newton<BS>(dp, bt, dq, ra, src, react);
+}
+
 template <int KT, int BS>
 __global__ __launch_bounds__(BS)
 __attribute__((amdgpu_waves_per_eu(KT == 1 ? CT_F32_WAVES_PER_EU : (KT == 2 ? 5 : 4))))
@@ -470,7 +742,8 @@ void k_run_f64(DevParams dp, DevBatch bt, DevQueue dq, RunArgs ra)
 // counters; resets the run's control block.  One workgroup of 1024; events
 // in blocks of 1024, each wave emitting the items of every 16th event.
 __global__ __launch_bounds__(1024) void k_init(DevBatch bt, DevQueue dq, int T, int bs, int chunk,
-                                               int64_t max_steps, int field_only, int repulsion)
+                                               int64_t max_steps, int field_only, int repulsion,
+                                               int newton)
 {
     __shared__ int wtot[16];
     __shared__ uint32_t s_base[1024];
@@ -491,12 +764,20 @@ __global__ __launch_bounds__(1024) void k_init(DevBatch bt, DevQueue dq, int T, 
         if (e < B) {
             const int n = bt.n_act[e];
             if (bt.n_hole[e] > 0 && (field_only || bt.call_steps[e] < max_steps)) {
-                const int tiles = (n + T - 1) / T;
-                int len = n;
-                if (repulsion) event_chunks(n, bs, chunk, len, nchunk);
-                items = tiles * nchunk;
-                dq.tiles_left[e * kEventLine] = tiles;
-                for (int j = 0; j < tiles; ++j) dq.chunks_left[dq.tile_base[e] + j] = nchunk;
+                if (newton) {
+                    const SymSplit sp = sym_split(n, chunk / kSymTile);
+                    nchunk = sp.R;
+                    items = sp.T * sp.R;
+                    dq.tiles_left[e * kEventLine] = sp.T;
+                    for (int j = 0; j < sp.T; ++j) dq.chunks_left[dq.tile_base[e] + j] = sym_expected(sp, j);
+                } else {
+                    const int tiles = (n + T - 1) / T;
+                    int len = n;
+                    if (repulsion) event_chunks(n, bs, chunk, len, nchunk);
+                    items = tiles * nchunk;
+                    dq.tiles_left[e * kEventLine] = tiles;
+                    for (int j = 0; j < tiles; ++j) dq.chunks_left[dq.tile_base[e] + j] = nchunk;
+                }
             } else {
                 atomicAdd(&n_done, 1u);
             }
@@ -683,6 +964,14 @@ hipError_t launch_run_t(const DevParams &dp, const DevBatch &bt, const DevQueue 
     return hipGetLastError();
 }
 
+int occupancy_newton()
+{
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, reinterpret_cast<const void *>(&k_run_newton<kSymTile>), kSymTile, 0);
+    return e == hipSuccess ? nb : -1;
+}
+
 template <int KT, int BS>
 int occupancy_t(int fp32)
 {
@@ -732,7 +1021,7 @@ hipError_t launch_init(const DevBatch &bt, const DevQueue &dq, const LaunchCfg &
                        int64_t max_steps, int field_only, int repulsion, hipStream_t s)
 {
     hipLaunchKernelGGL(k_init, dim3(1), dim3(1024), 0, s, bt, dq, cfg.bs * cfg.kt, cfg.bs,
-                       cfg.chunk, max_steps, field_only, repulsion);
+                       cfg.chunk, max_steps, field_only, repulsion, cfg.newton);
     return hipGetLastError();
 }
 
@@ -747,6 +1036,13 @@ hipError_t launch_run(const DevParams &dp, const DevBatch &bt, const DevQueue &d
 {
     if (bt.n_events <= 0 || grid <= 0) return hipSuccess;
     RunArgs ra{cfg.chunk, field_only, max_steps, idle_ticks(), field_out};
+    if (cfg.newton) {
+        if (!fp32 || cfg.kt != 1 || cfg.bs != kSymTile || cfg.chunk % kSymTile != 0 ||
+            cfg.chunk / kSymTile > kSymMaxC)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_run_newton<kSymTile>, dim3(grid), dim3(kSymTile), 0, s, dp, bt, dq, ra);
+        return hipGetLastError();
+    }
 #define CT_RUN_CASE(KT_, BS_) \
     if (cfg.kt == KT_ && cfg.bs == BS_) return launch_run_t<KT_, BS_>(dp, bt, dq, ra, fp32, grid, s);
     CT_LAUNCH_CASES(CT_RUN_CASE)
@@ -763,6 +1059,7 @@ hipError_t launch_summary(const DevBatch &bt, Sched *sc, hipStream_t s)
 // Resident workgroups per compute unit of the run kernel for a configuration.
 int run_occupancy(const LaunchCfg &cfg, int fp32)
 {
+    if (cfg.newton) return fp32 ? occupancy_newton() : -1;
 #define CT_OCC_CASE(KT_, BS_) \
     if (cfg.kt == KT_ && cfg.bs == BS_) return occupancy_t<KT_, BS_>(fp32);
     CT_LAUNCH_CASES(CT_OCC_CASE)

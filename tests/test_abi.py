@@ -91,7 +91,7 @@ def test_parameter_validation(ct):
     with pytest.raises(ct.CtError) as e:
         ct.ct_init_sensor(p)
     assert e.value.status == -1
-    for bits in (2, 8, 1 << 20):  # only CT_OPT_TIMING and CT_OPT_AUTOTUNE exist
+    for bits in (2, 16, 1 << 20):  # only CT_OPT_TIMING, CT_OPT_AUTOTUNE and CT_OPT_ONE_SIDED exist
         p = ct.make_params(Sensor())
         p.options = bits
         with pytest.raises(ct.CtError) as e:

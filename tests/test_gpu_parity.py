@@ -31,8 +31,8 @@ def ct():
     return ct
 
 
-def gpu_run(ct, sensor, batch, precision, launch=None, max_steps=0):
-    with ct.Simulator(sensor, precision, launch=launch) as sim:
+def gpu_run(ct, sensor, batch, precision, launch=None, max_steps=0, options=0):
+    with ct.Simulator(sensor, precision, launch=launch, options=options) as sim:
         r = sim.run(batch, max_steps)
     return r
 
@@ -295,6 +295,52 @@ def test_large_events_full_size(ct, make):
     df = np.abs(fractions(full32) - fractions(full64)).max()
     assert df <= FRACTION_TOL, (make.__name__, df)
     print(f"{make.__name__}: FP32 vs FP64 pixel fractions over full runs: {df:.2e}")
+
+
+@pytest.mark.parametrize("n", [131072, 131329])
+def test_newton_pair_split_limits(ct, n):
+    """FP32 field of one event at the Newton-pair limit (512 tiles of 256
+    holes: 257 partner offsets per tile, reaction partials in 256 slots) and
+    just past it (514 tiles: every ordered pair evaluated), on sampled targets
+    against the oracle within the FP32 bound; and the same state with
+    CT_OPT_ONE_SIDED."""
+    rng = np.random.default_rng(n)
+    xyz = rng.normal(size=(n, 3)) * [20.0, 20.0, 10.0] + [0.0, 0.0, 150.0]
+    s = Sensor(softening_um=0.01)
+    K = oracle.coulomb_k(s)
+    tg = np.sort(np.concatenate([rng.choice(n, size=200, replace=False), [0, n - 1]]))
+    ref = oracle.field_at(s, xyz, tg)
+    bound = _bound_at(xyz, tg, s.softening_um, K, True)
+    for opt in (0, ct.CT_OPT_ONE_SIDED):
+        with ct.Simulator(s, FP32, options=opt) as sim:
+            sim.seed(explicit_batch([xyz]))
+            E = sim.field()[tg]
+            assert sim.collect(carriers=False)["stats"].newton_pairs == (opt == 0)
+        err = np.abs(E - ref).max(axis=1)
+        assert np.all(err <= bound), (n, opt, (err / bound).max())
+
+
+def test_newton_pairs_against_one_sided(ct):
+    """The Newton-pair and one-sided FP32 kernels on the ragged batch: both
+    within the FP32 bar of the oracle, both with exact hole conservation, and
+    the same collection step for nearly every hole."""
+    rng = np.random.default_rng(5)
+    sizes = [1, 255, 256, 257, 511, 513, 2222, 3000]
+    evs = [rng.normal(size=(n, 3)) * 1.5 + [rng.uniform(-10, 10), rng.uniform(-10, 10),
+                                            rng.uniform(20, 80)] for n in sizes]
+    s = Sensor(seed=4)
+    b = explicit_batch(evs, first_event_id=7)
+    o = oracle.run(s, b)
+    res = {}
+    for opt in (0, ct.CT_OPT_ONE_SIDED):
+        for launch in (None, (1, 256, 512), (1, 256, 3840)):
+            g = gpu_run(ct, s, b, FP32, launch=launch, options=opt)
+            assert g["stats"].newton_pairs == (opt == 0)
+            assert_fp32_parity(g, o, f"newton {opt == 0} {launch}")
+            check_conservation(g, sizes)
+            res[(opt, launch)] = g
+    same = np.mean(res[(0, None)]["cstep"] == res[(ct.CT_OPT_ONE_SIDED, None)]["cstep"])
+    assert same >= 0.999, same
 
 
 # ------------------------------------------------------ closed forms
