@@ -261,8 +261,11 @@ ct_status ct_philox(ct_ctx *c, const uint32_t *counters, int64_t n, uint32_t *wo
  * of n holes is split into ceil(n / len) chunks of len sources, len being
  * chunk_len or, for events of more than 256 chunks, the shortest whole number
  * of tiles that keeps 256 chunks.  Each chunk of each target tile is one work
- * item.  0 leaves a value unchanged.  The block size and the chunk length set
- * the grouping of the field sum, so they change results within rounding. */
+ * item.  With Newton pairs (see CT_OPT_ONE_SIDED) a tile of 256 holes meets
+ * itself and about half of the other tiles, and an item takes chunk_len / 256
+ * of them (at most 15).  0 leaves a value unchanged.  The block size and the
+ * chunk length set the grouping of the field sum, so they change results
+ * within rounding. */
 ct_status ct_set_launch(ct_ctx *c, int32_t targets_per_thread, int32_t block_size,
                         int32_t chunk_len);
 
