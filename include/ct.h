@@ -263,7 +263,8 @@ ct_status ct_philox(ct_ctx *c, const uint32_t *counters, int64_t n, uint32_t *wo
  * of tiles that keeps 256 chunks.  Each chunk of each target tile is one work
  * item.  With Newton pairs (see CT_OPT_ONE_SIDED) a tile of 256 holes meets
  * itself and about half of the other tiles, and an item takes chunk_len / 256
- * of them (at most 15).  0 leaves a value unchanged.  The block size and the
+ * of them; longer chunks than 15 tiles, other block sizes or more targets per
+ * thread select the one-sided kernel.  0 leaves a value unchanged.  The block size and the
  * chunk length set the grouping of the field sum, so they change results
  * within rounding. */
 ct_status ct_set_launch(ct_ctx *c, int32_t targets_per_thread, int32_t block_size,
