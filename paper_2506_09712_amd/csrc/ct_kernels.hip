@@ -555,25 +555,44 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
         const int o0 = r * sp.C;
         const int o1 = min(o0 + sp.C, sp.newton ? sym_partners(sp.T, a) : sp.T);
         double ex = 0.0, ey = 0.0, ez = 0.0;
+        // the next partner tile's source is loaded into registers while the
+        // current one is computed
+        double px = 0.0, py = 0.0, pz = 0.0;
+        {
+            const int sj = (sp.newton ? (a + o0) % sp.T : o0) * BS + tid;
+            if (o0 < o1 && sj < n) {
+                px = bt.cx[base + sj];
+                py = bt.cy[base + sj];
+                pz = bt.cz[base + sj];
+            }
+        }
         for (int o = o0; o < o1; ++o) {
             const int pt = sp.newton ? (a + o) % sp.T : o;  // partner tile
             const bool reacts = sp.newton && o > 0;
             const int sj = pt * BS + tid;
-            float px = 1e18f, py = 1e18f, pz = 1e18f;
+            float fx = 1e18f, fy = 1e18f, fz = 1e18f;
             if (sj < n) {
-                px = (float)(bt.cx[base + sj] - rx);
-                py = (float)(bt.cy[base + sj] - ry);
-                pz = (float)(bt.cz[base + sj] - rz);
+                fx = (float)(px - rx);
+                fy = (float)(py - ry);
+                fz = (float)(pz - rz);
             }
             __syncthreads();  // the previous partner's sources and reactions are consumed
             float *d = src + 3 * (w * 128 + lane);
-            d[0] = px;
-            d[1] = py;
-            d[2] = pz;
-            d[192] = px;
-            d[193] = py;
-            d[194] = pz;
+            d[0] = fx;
+            d[1] = fy;
+            d[2] = fz;
+            d[192] = fx;
+            d[193] = fy;
+            d[194] = fz;
             __syncthreads();
+            if (o + 1 < o1) {
+                const int sn = (sp.newton ? (a + o + 1) % sp.T : o + 1) * BS + tid;
+                if (sn < n) {
+                    px = bt.cx[base + sn];
+                    py = bt.cy[base + sn];
+                    pz = bt.cz[base + sn];
+                }
+            }
             const int nblk = min(W, (n - pt * BS + 63) / 64);  // blocks holding holes
             float ax = 0.0f, ay = 0.0f, az = 0.0f;
             if (reacts) {
