@@ -493,6 +493,36 @@ __device__ __forceinline__ void sweep64(const float *__restrict__ p, float s2, f
     }
 }
 
+// A wave's 64 targets against the other 63 holes of their own block: lane l
+// meets hole l + s (mod 64) at the offsets s = 1..32, read from p = the
+// block's doubled entries + lane + 1, so that each pair of the block is met
+// once (offset 32 pairs l with l + 32 twice; only lanes below 32 count it).
+// After the 32 rotations lane l holds the reaction on hole (l + 33) mod 64.
+__device__ __forceinline__ void sweep_self(const float *__restrict__ p, float s2, float tx, float ty,
+                                           float tz, int lane, float &ax, float &ay, float &az,
+                                           float &bx, float &by, float &bz)
+{
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+        const float *q = p + 3 * u;
+        const float dx = tx - q[0];
+        const float dy = ty - q[1];
+        const float dz = tz - q[2];
+        float r2 = fmaf(dx, dx, s2);
+        r2 = fmaf(dy, dy, r2);
+        r2 = fmaf(dz, dz, r2);
+        const float inv = __builtin_amdgcn_rsqf(r2);
+        float inv3 = inv * inv * inv;
+        if (u == 31 && lane >= 32) inv3 = 0.0f;
+        ax = fmaf(dx, inv3, ax);
+        ay = fmaf(dy, inv3, ay);
+        az = fmaf(dz, inv3, az);
+        bx = lane_up(fmaf(-dx, inv3, bx));
+        by = lane_up(fmaf(-dy, inv3, by));
+        bz = lane_up(fmaf(-dz, inv3, bz));
+    }
+}
+
 // Most tiles one item contributes to: its own and one partner per offset.
 constexpr int kMaxTouch = kSymMaxC + 1;
 
@@ -595,7 +625,43 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
             }
             const int nblk = min(W, (n - pt * BS + 63) / 64);  // blocks holding holes
             float ax = 0.0f, ay = 0.0f, az = 0.0f;
-            if (reacts) {
+            if (sp.newton && o == 0) {
+                // the tile with itself: block pairs (w, w), (w, w + 1) and, for
+                // w < 2, (w, w + 2) (mod 4) meet every pair of the tile once;
+                // the reactions land on this tile's own holes
+                static_assert(W == 4, "four blocks per tile");
+                {
+                    float bx = 0.0f, by = 0.0f, bz = 0.0f;
+                    if (wave_has_targets)
+                        sweep_self(src + 3 * (w * 128 + lane + 1), dp.s2f, tx, ty, tz, lane, ax, ay,
+                                   az, bx, by, bz);
+                    float *q = react + 3 * (w * BS + w * 64 + ((lane + 33) & 63));
+                    q[0] = bx;
+                    q[1] = by;
+                    q[2] = bz;
+                }
+                for (int k = 1; k < W; ++k) {
+                    const int v = (w + k) & (W - 1);
+                    float bx = 0.0f, by = 0.0f, bz = 0.0f;
+                    if ((k == 1 || (k == 2 && w < 2)) && wave_has_targets && v < nblk)
+                        sweep64<true>(src + 3 * (v * 128 + lane), dp.s2f, tx, ty, tz, ax, ay, az,
+                                      bx, by, bz);
+                    float *q = react + 3 * (w * BS + v * 64 + lane);
+                    q[0] = bx;
+                    q[1] = by;
+                    q[2] = bz;
+                }
+                __syncthreads();
+                if (si < n) {
+#pragma unroll
+                    for (int w2 = 0; w2 < W; ++w2) {
+                        const float *q = react + 3 * (w2 * BS + tid);
+                        ex += (double)q[0];
+                        ey += (double)q[1];
+                        ez += (double)q[2];
+                    }
+                }
+            } else if (reacts) {
                 for (int v = 0; v < W; ++v) {
                     float bx = 0.0f, by = 0.0f, bz = 0.0f;
                     if (wave_has_targets && v < nblk)
