@@ -52,7 +52,8 @@ FP32_VECTOR_PEAK = 157.3e12   # MI355X FP32 vector FLOP/s (256 CU x 128 lanes x 
 SLOTS_PER_PAIR = 15
 # The Newton-pair kernel takes each unordered pair once for both holes: 3 sub,
 # 3 FMA, v_rsq (4 slots), 2 mul, 3 + 3 FMA and 3 DPP lane moves = 21 slots
-# for two ordered pairs (a tile with itself still costs 15 per ordered pair).
+# for two ordered pairs (within a tile too; the parked slots of ragged tiles
+# cost the same and count for nothing).
 # Executed FLOP: 24 per unordered pair (FMA as 2, rsqrt as 1), 12 per ordered.
 NEWTON_SLOTS_PER_PAIR = 10.5
 NEWTON_EXECUTED_FLOP_PER_PAIR = 12
