@@ -109,9 +109,9 @@ enum {
                              batch-shape bucket); the chosen configuration sets the grouping of
                              the field sum (see ct_set_launch) */
     CT_OPT_ONE_SIDED = 8u /* CT_FP32: evaluate every ordered pair (i, j) on its own.  By default
-                             a hole-only FP32 run with one target per thread and blocks of 256
-                             evaluates each unordered pair once and applies it to both holes
-                             (Eq. 4 is antisymmetric), in events of up to 131072 drifting holes;
+                             an FP32 run with one target per thread and blocks of 256
+                             evaluates each unordered pair once and applies it to both carriers
+                             (Eq. 4 is antisymmetric), in events of up to 131072 drifting carriers;
                              the two differ only in FP32 rounding */
 };
 

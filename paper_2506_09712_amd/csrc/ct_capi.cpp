@@ -456,15 +456,16 @@ ct_status set_device(ct_ctx *c)
 // memory is kept while it is large enough; its sequence words are cleared
 // whenever it is (re)allocated, so no stale ticket can match a generation.
 // The launch configuration with the Newton-pair kernel switched on where it
-// applies: FP32 repulsion among holes only, one target per thread, blocks
-// of kSymTile, at most kSymMaxC tiles per chunk.
+// applies: FP32 repulsion, one target per thread, blocks of kSymTile, at
+// most kSymMaxC tiles per chunk (with electrons, the kernel that carries the
+// carriers' charges).
 ct::LaunchCfg resolve_cfg(const ct_ctx *c, ct::LaunchCfg cfg)
 {
     const uint32_t f = c->p.physics_flags;
-    cfg.newton = c->p.precision == CT_FP32 && (f & CT_REPULSION) && !(f & CT_ELECTRONS) &&
-                 !(f & CT_SPHERICAL) && !(c->p.options & CT_OPT_ONE_SIDED) && cfg.kt == 1 &&
-                 cfg.bs == ct::kSymTile && cfg.chunk % ct::kSymTile == 0 &&
-                 cfg.chunk / ct::kSymTile <= ct::kSymMaxC;
+    const bool on = c->p.precision == CT_FP32 && (f & CT_REPULSION) && !(f & CT_SPHERICAL) &&
+                    !(c->p.options & CT_OPT_ONE_SIDED) && cfg.kt == 1 && cfg.bs == ct::kSymTile &&
+                    cfg.chunk % ct::kSymTile == 0 && cfg.chunk / ct::kSymTile <= ct::kSymMaxC;
+    cfg.newton = on ? ((f & CT_ELECTRONS) ? 2 : 1) : 0;
     return cfg;
 }
 
@@ -1033,7 +1034,7 @@ ct_status ct_collect(ct_ctx *c, int32_t *pixel_counts, double *xyz, int32_t *col
         r.block_size = spherical(c) ? ct::kSphBlock : c->cfg.bs;
         r.chunk_len = spherical(c) ? 0 : c->cfg.chunk;
         r.workgroups = c->grid + (spherical(c) ? c->grid_shared : 0);
-        r.newton_pairs = resolve_cfg(c, c->cfg).newton;
+        r.newton_pairs = resolve_cfg(c, c->cfg).newton != 0;
         *stats = r;
     }
     return CT_OK;

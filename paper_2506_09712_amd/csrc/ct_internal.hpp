@@ -121,7 +121,8 @@ struct LaunchCfg {
     int kt;        // targets per thread
     int bs;        // block size = sources per LDS tile
     int chunk;     // source chunk length (a multiple of bs; events longer than this are split)
-    int newton;    // 1: FP32 pair kernel that takes each unordered pair once (kt 1, bs 256)
+    int newton;    // FP32 pair kernel that takes each unordered pair once (kt 1, bs 256):
+                   // 1 holes only, 2 holes and electrons; 0 every ordered pair
 };
 
 // Parameters of the event generator (Sec. 4.2), precomputed on the host.

@@ -448,7 +448,7 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
     }
 }
 
-// ------------------------------------------------- Newton pairs (FP32, holes)
+// ------------------------------------------------------ Newton pairs (FP32)
 
 // Lane l receives the value of lane l + 1 (mod 64): DPP wave rotate.
 __device__ __forceinline__ float lane_up(float v)
@@ -464,10 +464,14 @@ __device__ __forceinline__ float lane_up(float v)
 // antisymmetry) in b, which moves one lane down after each step: after 64
 // steps every lane holds the reaction on its own source.  Without REACT all
 // lanes meet source s at step s (broadcast reads) and b is untouched.
-template <bool REACT>
-__device__ __forceinline__ void sweep64(const float *__restrict__ p, float s2, float tx, float ty,
-                                        float tz, float &ax, float &ay, float &az, float &bx,
-                                        float &by, float &bz)
+// With Q (holes and electrons), pq holds the sources' charges (+1 / -1) at
+// the entries of p, and qi is the target's: the target receives q_j times the
+// pair term, the source minus q_i times it.
+template <bool REACT, bool Q>
+__device__ __forceinline__ void sweep64(const float *__restrict__ p, const float *__restrict__ pq,
+                                        float s2, float tx, float ty, float tz, float qi,
+                                        float &ax, float &ay, float &az, float &bx, float &by,
+                                        float &bz)
 {
     for (int s0 = 0; s0 < 64; s0 += CT_PAIR_UNROLL) {
 #pragma unroll
@@ -481,13 +485,15 @@ __device__ __forceinline__ void sweep64(const float *__restrict__ p, float s2, f
             r2 = fmaf(dz, dz, r2);
             const float inv = __builtin_amdgcn_rsqf(r2);
             const float inv3 = inv * inv * inv;
-            ax = fmaf(dx, inv3, ax);
-            ay = fmaf(dy, inv3, ay);
-            az = fmaf(dz, inv3, az);
+            const float ti = Q ? inv3 * pq[s0 + u] : inv3;
+            ax = fmaf(dx, ti, ax);
+            ay = fmaf(dy, ti, ay);
+            az = fmaf(dz, ti, az);
             if constexpr (REACT) {
-                bx = lane_up(fmaf(-dx, inv3, bx));
-                by = lane_up(fmaf(-dy, inv3, by));
-                bz = lane_up(fmaf(-dz, inv3, bz));
+                const float tj = Q ? inv3 * qi : inv3;
+                bx = lane_up(fmaf(-dx, tj, bx));
+                by = lane_up(fmaf(-dy, tj, by));
+                bz = lane_up(fmaf(-dz, tj, bz));
             }
         }
     }
@@ -498,9 +504,11 @@ __device__ __forceinline__ void sweep64(const float *__restrict__ p, float s2, f
 // block's doubled entries + lane + 1, so that each pair of the block is met
 // once (offset 32 pairs l with l + 32 twice; only lanes below 32 count it).
 // After the 32 rotations lane l holds the reaction on hole (l + 33) mod 64.
-__device__ __forceinline__ void sweep_self(const float *__restrict__ p, float s2, float tx, float ty,
-                                           float tz, int lane, float &ax, float &ay, float &az,
-                                           float &bx, float &by, float &bz)
+template <bool Q>
+__device__ __forceinline__ void sweep_self(const float *__restrict__ p, const float *__restrict__ pq,
+                                           float s2, float tx, float ty, float tz, float qi, int lane,
+                                           float &ax, float &ay, float &az, float &bx, float &by,
+                                           float &bz)
 {
 #pragma unroll
     for (int u = 0; u < 32; ++u) {
@@ -514,21 +522,24 @@ __device__ __forceinline__ void sweep_self(const float *__restrict__ p, float s2
         const float inv = __builtin_amdgcn_rsqf(r2);
         float inv3 = inv * inv * inv;
         if (u == 31 && lane >= 32) inv3 = 0.0f;
-        ax = fmaf(dx, inv3, ax);
-        ay = fmaf(dy, inv3, ay);
-        az = fmaf(dz, inv3, az);
-        bx = lane_up(fmaf(-dx, inv3, bx));
-        by = lane_up(fmaf(-dy, inv3, by));
-        bz = lane_up(fmaf(-dz, inv3, bz));
+        const float ti = Q ? inv3 * pq[u] : inv3;
+        const float tj = Q ? inv3 * qi : inv3;
+        ax = fmaf(dx, ti, ax);
+        ay = fmaf(dy, ti, ay);
+        az = fmaf(dz, ti, az);
+        bx = lane_up(fmaf(-dx, tj, bx));
+        by = lane_up(fmaf(-dy, tj, by));
+        bz = lane_up(fmaf(-dz, tj, bz));
     }
 }
 
 // Most tiles one item contributes to: its own and one partner per offset.
 constexpr int kMaxTouch = kSymMaxC + 1;
 
-// The persistent loop with the Newton-pair split of the field (events of
-// holes only, FP32, one target per thread, tiles of kSymTile; the split is
-// described with sym_split).  An item stages each partner tile in LDS as
+// The persistent loop with the Newton-pair split of the field (FP32, one
+// target per thread, tiles of kSymTile; the split is described with
+// sym_split; with Q the events hold holes and electrons, whose charges are
+// staged beside the sources).  An item stages each partner tile in LDS as
 // four doubled blocks of 64; every wave sweeps its 64 targets over them.
 // The reactions of the four waves are summed per source in wave order (FP64)
 // into the partner's partial slot; the target side folds each partner
@@ -537,9 +548,9 @@ constexpr int kMaxTouch = kSymMaxC + 1;
 // tile sums its slots in slot order and updates it, and the one that
 // completes the event's last tile compacts the event and queues its next
 // step, as in run_loop.
-template <int BS>
+template <int BS, bool Q>
 __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const DevQueue &dq,
-                                const RunArgs &ra, float *src, float *react)
+                                const RunArgs &ra, float *src, float *react, float *sq)
 {
     static_assert(BS == kSymTile, "one target per thread over tiles of kSymTile");
     constexpr int W = BS / 64;
@@ -547,7 +558,7 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
     __shared__ int s_go;
     __shared__ int s_wcount[kCompactChunks * W];
     __shared__ double s_wsum[3 * W];
-    __shared__ int s_items, s_kept;
+    __shared__ int s_items, s_kept, s_nh;
     __shared__ uint32_t s_t0;
     __shared__ int s_fin[kMaxTouch];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -566,6 +577,7 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
         if (!s_go) break;
         const QItem it = s_item;
         const int b = it.e, n = it.n, a = it.tile, r = it.chunk;
+        const int nh = Q ? it.nh : n;  // the first nh slots hold holes, the rest electrons
         const int base = bt.off[b];
         const int n0 = bt.off[b + 1] - base;
         set_item_priority(bt.ref[4 * b + 2], dp.H);
@@ -576,6 +588,7 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
         // with them underflows to 0 (they also act as sources here)
         const int si = a * BS + tid;
         float tx = 1e18f, ty = 1e18f, tz = 1e18f;
+        const float qi = si < nh ? 1.0f : (si < n ? -1.0f : 0.0f);
         if (si < n) {
             tx = (float)(bt.cx[base + si] - rx);
             ty = (float)(bt.cy[base + si] - ry);
@@ -614,6 +627,11 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
             d[192] = fx;
             d[193] = fy;
             d[194] = fz;
+            if constexpr (Q) {
+                const float qs = sj < nh ? 1.0f : (sj < n ? -1.0f : 0.0f);
+                sq[w * 128 + lane] = qs;
+                sq[w * 128 + 64 + lane] = qs;
+            }
             __syncthreads();
             if (o + 1 < o1) {
                 const int sn = (sp.newton ? (a + o + 1) % sp.T : o + 1) * BS + tid;
@@ -633,8 +651,8 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
                 {
                     float bx = 0.0f, by = 0.0f, bz = 0.0f;
                     if (wave_has_targets)
-                        sweep_self(src + 3 * (w * 128 + lane + 1), dp.s2f, tx, ty, tz, lane, ax, ay,
-                                   az, bx, by, bz);
+                        sweep_self<Q>(src + 3 * (w * 128 + lane + 1), sq + w * 128 + lane + 1, dp.s2f,
+                                      tx, ty, tz, qi, lane, ax, ay, az, bx, by, bz);
                     float *q = react + 3 * (w * BS + w * 64 + ((lane + 33) & 63));
                     q[0] = bx;
                     q[1] = by;
@@ -644,8 +662,8 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
                     const int v = (w + k) & (W - 1);
                     float bx = 0.0f, by = 0.0f, bz = 0.0f;
                     if ((k == 1 || (k == 2 && w < 2)) && wave_has_targets && v < nblk)
-                        sweep64<true>(src + 3 * (v * 128 + lane), dp.s2f, tx, ty, tz, ax, ay, az,
-                                      bx, by, bz);
+                        sweep64<true, Q>(src + 3 * (v * 128 + lane), sq + v * 128 + lane, dp.s2f, tx,
+                                         ty, tz, qi, ax, ay, az, bx, by, bz);
                     float *q = react + 3 * (w * BS + v * 64 + lane);
                     q[0] = bx;
                     q[1] = by;
@@ -665,8 +683,8 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
                 for (int v = 0; v < W; ++v) {
                     float bx = 0.0f, by = 0.0f, bz = 0.0f;
                     if (wave_has_targets && v < nblk)
-                        sweep64<true>(src + 3 * (v * 128 + lane), dp.s2f, tx, ty, tz, ax, ay, az,
-                                      bx, by, bz);
+                        sweep64<true, Q>(src + 3 * (v * 128 + lane), sq + v * 128 + lane, dp.s2f, tx,
+                                         ty, tz, qi, ax, ay, az, bx, by, bz);
                     float *q = react + 3 * (w * BS + v * 64 + lane);
                     q[0] = bx;
                     q[1] = by;
@@ -690,7 +708,8 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
             } else if (wave_has_targets) {
                 float bx = 0.0f, by = 0.0f, bz = 0.0f;
                 for (int v = 0; v < nblk; ++v)
-                    sweep64<false>(src + 3 * v * 128, dp.s2f, tx, ty, tz, ax, ay, az, bx, by, bz);
+                    sweep64<false, Q>(src + 3 * v * 128, sq + v * 128, dp.s2f, tx, ty, tz, qi, ax, ay,
+                                      az, bx, by, bz);
             }
             ex += (double)ax;
             ey += (double)ay;
@@ -751,7 +770,7 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
                 break;
             }
             int holes_kept = 0;
-            const int kept = compact_event<BS>(bt, b, n, n, dp.H, 1, s_wcount, s_wsum, holes_kept);
+            const int kept = compact_event<BS>(bt, b, n, nh, dp.H, 1, s_wcount, s_wsum, holes_kept);
             if (tid == 0) {
                 int items = 0;
                 uint32_t t0q = 0;
@@ -767,6 +786,7 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
                 if (items == 0) add_relaxed(&sc->done.v, 1u);
                 s_items = items;
                 s_kept = kept;
+                s_nh = holes_kept;
                 s_t0 = t0q;
             }
             __syncthreads();
@@ -783,7 +803,7 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
                     st_dev(q + 1, i / s2.R);
                     st_dev(q + 2, i % s2.R);
                     st_dev(q + 3, s_kept);
-                    st_dev(q + 4, s_kept);
+                    st_dev(q + 4, s_nh);
                 }
                 wait_own_stores();
                 __syncthreads();
@@ -796,13 +816,16 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
     }
 }
 
-template <int BS>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(CT_F32_WAVES_PER_EU)))
+// With charges the LDS of 8 workgroups no longer fits a CU: 7 per CU.
+template <int BS, bool Q>
+__global__ __launch_bounds__(BS)
+__attribute__((amdgpu_waves_per_eu(Q ? CT_F32_WAVES_PER_EU - 1 : CT_F32_WAVES_PER_EU)))
 void k_run_newton(DevParams dp, DevBatch bt, DevQueue dq, RunArgs ra)
 {
     __shared__ float src[3 * 2 * BS];             // four blocks of 64 sources, each twice
     __shared__ float react[3 * BS * (BS / 64)];   // reactions per wave and source
-    run_loop_newton<BS>(dp, bt, dq, ra, src, react);
+    __shared__ float sq[Q ? 2 * BS : 1];          // the sources' charges (holes and electrons)
+    run_loop_newton<BS, Q>(dp, bt, dq, ra, src, react, sq);
 }
 
 template <int KT, int BS>
@@ -1049,11 +1072,12 @@ hipError_t launch_run_t(const DevParams &dp, const DevBatch &bt, const DevQueue 
     return hipGetLastError();
 }
 
-int occupancy_newton()
+int occupancy_newton(bool charged)
 {
     int nb = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, reinterpret_cast<const void *>(&k_run_newton<kSymTile>), kSymTile, 0);
+    const void *k = charged ? reinterpret_cast<const void *>(&k_run_newton<kSymTile, true>)
+                            : reinterpret_cast<const void *>(&k_run_newton<kSymTile, false>);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kSymTile, 0);
     return e == hipSuccess ? nb : -1;
 }
 
@@ -1125,7 +1149,12 @@ hipError_t launch_run(const DevParams &dp, const DevBatch &bt, const DevQueue &d
         if (!fp32 || cfg.kt != 1 || cfg.bs != kSymTile || cfg.chunk % kSymTile != 0 ||
             cfg.chunk / kSymTile > kSymMaxC)
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_run_newton<kSymTile>, dim3(grid), dim3(kSymTile), 0, s, dp, bt, dq, ra);
+        if (cfg.newton == 2)
+            hipLaunchKernelGGL((k_run_newton<kSymTile, true>), dim3(grid), dim3(kSymTile), 0, s, dp,
+                               bt, dq, ra);
+        else
+            hipLaunchKernelGGL((k_run_newton<kSymTile, false>), dim3(grid), dim3(kSymTile), 0, s, dp,
+                               bt, dq, ra);
         return hipGetLastError();
     }
 #define CT_RUN_CASE(KT_, BS_) \
@@ -1144,7 +1173,7 @@ hipError_t launch_summary(const DevBatch &bt, Sched *sc, hipStream_t s)
 // Resident workgroups per compute unit of the run kernel for a configuration.
 int run_occupancy(const LaunchCfg &cfg, int fp32)
 {
-    if (cfg.newton) return fp32 ? occupancy_newton() : -1;
+    if (cfg.newton) return fp32 ? occupancy_newton(cfg.newton == 2) : -1;
 #define CT_OCC_CASE(KT_, BS_) \
     if (cfg.kt == KT_ && cfg.bs == BS_) return occupancy_t<KT_, BS_>(fp32);
     CT_LAUNCH_CASES(CT_OCC_CASE)
