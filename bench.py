@@ -239,7 +239,7 @@ def main():
                      "traffic": traffic, "traffic_note": traffic_note,
                      "algorithmic_bytes_per_launch": ALG_BYTES_PER_HOLE_STEP * hsteps / max(launches, 1),
                      "hole_steps_per_launch": hsteps / max(launches, 1),
-                     "kernel": "k_run_newton<256>" if newton else
+                     "kernel": f"k_run_newton<256, {'true' if n_carriers != n_holes else 'false'}>" if newton else
                                f"k_run_f32<{st.targets_per_thread},{st.block_size}>",
                      "pair_evaluation": "each unordered pair once, applied to both holes" if newton
                                         else "every ordered pair",
