@@ -63,9 +63,15 @@ def test_single_8kev_pairs_fp64_and_fp32(ct):
     assert np.array_equal(g["steps"], o["steps"])
     _holes_in_pixels(g, [2222])
     g32 = gpu_run(ct, s, b, FP32)
+    assert g32["stats"].newton_pairs == 1  # charged Newton pairs
     df = assert_fp32_parity(g32, o, "single_8kev pairs fp32")
     _holes_in_pixels(g32, [2222])
-    print(f"single_8kev with electrons: fp64 endpoint error {err:.2e} um, fp32 fraction {df:.2e}")
+    g1 = gpu_run(ct, s, b, FP32, options=ct.CT_OPT_ONE_SIDED)
+    assert g1["stats"].newton_pairs == 0
+    df1 = assert_fp32_parity(g1, o, "single_8kev pairs fp32, every ordered pair")
+    _holes_in_pixels(g1, [2222])
+    print(f"single_8kev with electrons: fp64 endpoint error {err:.2e} um, fp32 fraction {df:.2e} "
+          f"(Newton pairs), {df1:.2e} (every ordered pair)")
 
 
 @pytest.mark.parametrize("launch", [None, (1, 128, 128), (2, 256, 256), (4, 256, 1024), (1, 64, 64)])
