@@ -214,15 +214,20 @@ ct_status ct_bind_workspace(ct_ctx *c, void *device_ptr, size_t bytes);
 ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
                          uint64_t first_event_id);
 
-/* Advance every event until all its holes are collected or it has taken
- * max_steps steps in this call (max_steps <= 0: the context's max_steps).
+/* The time-step loop of Algorithm 1 (Appendix A): while an event has holes
+ * drifting, evaluate the field of Eq. 4 at every drifting carrier from the
+ * step-start positions, then move each carrier by Eqs. 3, 5 and 6 and
+ * collect the holes that reach the pixel plane; the loop of an event ends
+ * when its last hole is collected (Algorithm 1's loop condition: every hole
+ * has reached the electrode) or after max_steps steps in this call
+ * (max_steps <= 0: the context's max_steps).
  * Events advance independently: one persistent kernel works through a
  * device queue of (event, target tile, source chunk) items, and finishing an
  * event's step queues its next one, with no device-wide barrier between
  * steps.  steps_done (nullable): the most steps any event took in this call;
  * n_active (nullable): holes still drifting.  Returns CT_OK when none is
  * left, CT_EMAXSTEPS otherwise (state kept; call again to continue).  The
- * queue holds about 512 steps of the batch at its seeded size (environment
+ * queue holds about 1024 steps of the batch at its seeded size (environment
  * variable CT_QUEUE_STEPS, read at seeding, sets another count); when it
  * fills, the events it cannot take are parked and run again by the same
  * call, which costs time but never changes results.  If no event step is
@@ -230,7 +235,9 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
  * returns CT_EDEVICE (the context must then be destroyed). */
 ct_status ct_step(ct_ctx *c, int64_t max_steps, int64_t *steps_done, int64_t *n_active);
 
-/* Copy results to host arrays (each nullable):
+/* The output of Algorithm 1 (the final carrier positions it returns) and the
+ * carrier count per pixel of the collected holes (Sec. 4.2), copied to host
+ * arrays (each nullable):
  *   pixel_counts [B][grid_n*grid_n + 1]  collected holes per pixel, last = outside the grid
  *                                         (electrons are never counted)
  *   xyz          [N_total][3]            position at collection, or current position if

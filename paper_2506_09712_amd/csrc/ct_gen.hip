@@ -20,40 +20,51 @@ namespace {
 
 constexpr uint32_t kDomainGenerator = 5u;
 
-// Regularized lower incomplete gamma P(a, x) for a > 0, x >= 0 (FP64): the
-// power series x^a e^-x / Gamma(a + 1) * sum x^n / ((a + 1) ... (a + n)) for
-// x < a + 1, else 1 - Q with Q from Legendre's continued fraction
-// e^-x x^a / Gamma(a) * 1 / (x + 1 - a - 1 (1 - a) / (x + 3 - a - ...)),
-// evaluated by the modified Lentz method.
+// Regularized lower incomplete gamma P(a, x) for a > 0, x >= 0 (FP64), by
+// the two classical expansions, each used where it converges fast:
+//  * x < a + 1: the power series of DLMF 8.7.1 (Abramowitz and Stegun
+//    6.5.29), P = x^a e^-x sum_k x^k / Gamma(a + k + 1), written as
+//    x^a e^-x / Gamma(a) times sum_k x^k / (a (a + 1) ... (a + k)), each term
+//    the previous one times x / (a + k);
+//  * otherwise P = 1 - Q, Q = x^a e^-x / Gamma(a) times the even contraction
+//    of the continued fraction of DLMF 8.9.2 (Abramowitz and Stegun 6.5.31),
+//    1 / (x + 1 - a - 1 (1 - a) / (x + 3 - a - 2 (2 - a) / (x + 5 - a - ...))),
+//    evaluated front to back with the modified Lentz algorithm (Lentz,
+//    Appl. Opt. 15, 668 (1976); Thompson and Barnett, J. Comput. Phys. 64,
+//    490 (1986)): the convergent is a running product of ratios of
+//    successive numerator and denominator recurrences.
 __device__ double gamma_p(double a, double x)
 {
     if (!(x > 0.0)) return 0.0;
-    const double lead = -x + a * log(x) - lgamma(a);
+    const double log_prefactor = -x + a * log(x) - lgamma(a);  // log of x^a e^-x / Gamma(a)
     if (x < a + 1.0) {
-        double ap = a, del = 1.0 / a, sum = del;
-        for (int n = 0; n < 400; ++n) {
-            ap += 1.0;
-            del *= x / ap;
-            sum += del;
-            if (fabs(del) < fabs(sum) * 1e-17) break;
+        double shifted = a, term = 1.0 / a, series = term;
+        for (int k = 0; k < 400; ++k) {
+            shifted += 1.0;
+            term *= x / shifted;
+            series += term;
+            if (fabs(term) < fabs(series) * 1e-17) break;
         }
-        return sum * exp(lead);
+        return series * exp(log_prefactor);
     }
-    const double tiny = 1e-300;
-    double b = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
-    for (int i = 1; i < 400; ++i) {
-        const double an = -i * (i - a);
-        b += 2.0;
-        d = an * d + b;
-        if (fabs(d) < tiny) d = tiny;
-        c = b + an / c;
-        if (fabs(c) < tiny) c = tiny;
-        d = 1.0 / d;
-        const double del = d * c;
-        h *= del;
-        if (fabs(del - 1.0) < 1e-17) break;
+    // Lentz: partial numerators -k (k - a), partial denominators x + 2k + 1 - a;
+    // `floor_` replaces a recurrence ratio that would vanish
+    const double floor_ = 1e-300;
+    double denom = x + 1.0 - a, num_ratio = 1.0 / floor_, den_ratio = 1.0 / denom;
+    double convergent = den_ratio;
+    for (int k = 1; k < 400; ++k) {
+        const double numer = -k * (k - a);
+        denom += 2.0;
+        den_ratio = numer * den_ratio + denom;
+        if (fabs(den_ratio) < floor_) den_ratio = floor_;
+        num_ratio = denom + numer / num_ratio;
+        if (fabs(num_ratio) < floor_) num_ratio = floor_;
+        den_ratio = 1.0 / den_ratio;
+        const double step = den_ratio * num_ratio;
+        convergent *= step;
+        if (fabs(step - 1.0) < 1e-17) break;
     }
-    return 1.0 - exp(lead) * h;
+    return 1.0 - exp(log_prefactor) * convergent;
 }
 
 // CDF of the symmetric GGD (Eq. 8) of scale alpha and shape beta at x.

@@ -126,6 +126,54 @@ def test_mobility_limits_and_hole_values(oracle_lib):
     assert oracle_lib.mobility(s1, 2.0) == pytest.approx(22.5, rel=1e-14)
 
 
+# Caughey-Thomas parameters of silicon from the Jacoboni-Canali temperature
+# laws (Jacoboni et al., Solid-State Electron. 20, 77 (1977)) evaluated by
+# hand at 293 K: mu0 = vm / Ec [um^2/(V ns)], Ec [V/um], beta, vm [um/ns].
+# Holes: vm = 1.62e8 T^-0.52 cm/s, Ec = 1.24 T^1.68 V/cm, beta = 0.46 T^0.17;
+# electrons: vm = 1.53e9 T^-0.87 cm/s, Ec = 1.01 T^1.55 V/cm, beta = 2.57e-2 T^0.66.
+JC_293K = {
+    "holes": dict(mu0=48.863, ec=1.7289, beta=1.2082, vm=84.478, v047=19.6502),
+    "electrons": dict(mu0=162.387, ec=0.67292, beta=1.09161, vm=109.274, v047=47.5586),
+}
+# The same laws in the form referenced to 300 K in which device simulators
+# tabulate them (Canali et al., IEEE Trans. Electron Devices 22, 1045 (1975)):
+# v_sat(T) = v_sat(300 K) (300 / T)^a, beta(T) = beta(300 K) (T / 300)^b, and
+# the lattice-limited low-field mobility of silicon falls as T^-2.42
+# (electrons) and T^-2.20 (holes) (Jacoboni et al. 1977; Sze, Physics of
+# Semiconductor Devices).  Values in cm/s.
+CANALI_300K = {
+    "holes": dict(vsat=8.37e6, a=0.52, beta=1.213, b=0.17, mu_exp=-2.20, mu0_range=(450, 490)),
+    "electrons": dict(vsat=1.07e7, a=0.87, beta=1.109, b=0.66, mu_exp=-2.42, mu0_range=(1400, 1560)),
+}
+
+
+@pytest.mark.parametrize("species", ["holes", "electrons"])
+def test_mobility_laws_pinned_to_published_values(oracle_lib, species):
+    """A mistyped prefactor or exponent of the temperature laws, or a wrong
+    form of the field dependence, fails one of these: the four parameters
+    and the drift velocity at a mid-range field (0.47 V/um, the middle of the
+    150 V / 320 um sensor) at 293 K to 1e-4, and the saturation velocity,
+    beta and low-field mobility against the 300 K-referenced tabulation at
+    250, 300 and 350 K."""
+    el = species == "electrons"
+    s = _sensor(temperature_k=293.0, electrons=el)
+    mu0, ec, beta = oracle_lib.mobility_params(s, electron=el)
+    ref = JC_293K[species]
+    assert mu0 == pytest.approx(ref["mu0"], rel=1e-4)
+    assert ec == pytest.approx(ref["ec"], rel=1e-4)
+    assert beta == pytest.approx(ref["beta"], rel=1e-4)
+    assert mu0 * ec == pytest.approx(ref["vm"], rel=1e-4)
+    assert oracle_lib.mobility(s, 0.47, electron=el) * 0.47 == pytest.approx(ref["v047"], rel=1e-4)
+    c = CANALI_300K[species]
+    mu300 = oracle_lib.mobility_params(_sensor(temperature_k=300.0, electrons=el), electron=el)[0]
+    assert c["mu0_range"][0] < mu300 * 10 < c["mu0_range"][1]
+    for T in (250.0, 300.0, 350.0):
+        m, e, b = oracle_lib.mobility_params(_sensor(temperature_k=T, electrons=el), electron=el)
+        assert m * e * 1e5 == pytest.approx(c["vsat"] * (300.0 / T) ** c["a"], rel=4e-3), T
+        assert b == pytest.approx(c["beta"] * (T / 300.0) ** c["b"], rel=5e-4), T
+        assert m / mu300 == pytest.approx((T / 300.0) ** c["mu_exp"], rel=1e-9), T
+
+
 # ---------------------------------------------------------- drift field
 
 def test_drift_field_integrates_to_bias(oracle_lib):
