@@ -60,10 +60,12 @@ struct Sched {
 constexpr int kEventLine = 16;  // int32 words
 
 // Device view of a batch.  Slots [off[b], off[b] + n_act[b]) of the position
-// arrays hold the drifting carriers of event b, compacted and in carrier
-// order: its n_hole[b] drifting holes first, then its drifting electrons
-// (carrier indices below nh0[b] are holes).  Slots [off[b], off[b + 1])
-// belong to event b for the whole run.
+// arrays hold the drifting carriers of event b, compacted in their seeded
+// slot order: its n_hole[b] drifting holes first, then its drifting
+// electrons (carrier indices below nh0[b] are holes), each species in
+// carrier order, or deposit by deposit for an event of several deposits
+// (deposit_major).  Slots [off[b], off[b + 1]) belong to event b for the
+// whole run.
 struct DevBatch {
     int32_t n_events;
     int32_t n_total;
@@ -75,7 +77,8 @@ struct DevBatch {
     int64_t *ev_step;       // [B] absolute step of the event
     int64_t *ev_taken;      // [B] steps taken since seeding
     int64_t *call_steps;    // [B] steps taken in the current ct_step call
-    double *ref;            // [B][4] reference point (centroid) for FP32 coordinates
+    double *ref;            // [B][4] centroid of the drifting carriers (the spherical
+                            //        model's centre; wave priorities)
     double *cx, *cy, *cz;   // [N] current positions (compacted)
     double *nx, *ny, *nz;   // [N] positions after the step (same slots)
     int32_t *idx;           // [N] carrier index within its event, per slot (compacted)
@@ -250,6 +253,27 @@ __host__ __device__ inline void event_chunks(int n, int bs, int chunk, int &len,
     len = chunk > min_len ? chunk : min_len;
     if (len < bs) len = bs;
     count = n > 0 ? (n + len - 1) / len : 0;
+}
+
+// Carrier of slot s among the n carriers of one species spread over nd
+// deposits (carrier k sits on deposit k mod nd): slots run deposit by
+// deposit, each deposit's carriers in increasing order, so that every tile
+// of consecutive slots is spatially compact (FP32 coordinates are formed
+// relative to a tile's own centroid).  A bijection of [0, n).
+__host__ __device__ inline int deposit_major(int s, int n, int nd)
+{
+    if (nd <= 1) return s;
+    const int q = n / nd, r = n % nd;  // deposits below r hold q + 1 carriers
+    int d, m;
+    if (s < r * (q + 1)) {
+        d = s / (q + 1);
+        m = s - d * (q + 1);
+    } else {
+        const int t = s - r * (q + 1);
+        d = r + t / q;
+        m = t - (d - r) * q;
+    }
+    return d + m * nd;
 }
 
 }  // namespace ct

@@ -44,8 +44,24 @@ __device__ __forceinline__ void field_or_advance(const DevParams &dp, const DevB
 
 // ------------------------------------------------------------- pair loops
 
-// FP32: targets and sources relative to the event centroid.  Sources past the
-// end of a tile are parked at 1e18 um, where the pair term underflows to 0.
+// Origin of the FP32 coordinates of a work item: the FP64 position of the
+// first drifting carrier of its target tile at the step start (the same for
+// every item of the tile, and a function of the event alone).  Tiles are runs
+// of consecutive slots, and a multi-deposit event's slots run deposit by
+// deposit, so a tile's carriers lie close to its first one: FP32 coordinates
+// relative to it resolve close pairs far better than coordinates relative to
+// the centroid of an event spread over a long track.
+__device__ __forceinline__ void tile_origin(const DevBatch &bt, int slot, double &ox, double &oy,
+                                            double &oz)
+{
+    ox = bt.cx[slot];
+    oy = bt.cy[slot];
+    oz = bt.cz[slot];
+}
+
+// FP32: targets and sources relative to the target tile's origin.  Sources
+// past the end of a tile are parked at 1e18 um, where the pair term
+// underflows to 0.
 #ifndef CT_PAIR_UNROLL
 #define CT_PAIR_UNROLL 8
 #endif
@@ -247,7 +263,8 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
         if (repulsion) {
             if constexpr (F32) {
                 float4 *tile = static_cast<float4 *>(lds);
-                const double rx = bt.ref[4 * b + 0], ry = bt.ref[4 * b + 1], rz = bt.ref[4 * b + 2];
+                double rx, ry, rz;
+                tile_origin(bt, base + t0, rx, ry, rz);
                 float tx[KT], ty[KT], tz[KT];
 #pragma unroll
                 for (int m = 0; m < KT; ++m) {
@@ -582,8 +599,9 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
         const int n0 = bt.off[b + 1] - base;
         set_item_priority(bt.ref[4 * b + 2], dp.H);
         const SymSplit sp = sym_split(n, ctiles);
-        const double rx = bt.ref[4 * b + 0], ry = bt.ref[4 * b + 1], rz = bt.ref[4 * b + 2];
         const int64_t po = dq.part_off[b];
+        double rx, ry, rz;
+        tile_origin(bt, base + a * BS, rx, ry, rz);
         // targets past the end are parked far away, where every pair term
         // with them underflows to 0 (they also act as sources here)
         const int si = a * BS + tid;
@@ -977,7 +995,10 @@ __global__ __launch_bounds__(256) void k_compact(DevParams dp, DevBatch bt)
 }
 
 // Initial clouds (Algorithm 1, initialisation; Eq. 2 width).  One thread per
-// carrier; the event is found by binary search over the slot offsets.
+// slot; the event is found by binary search over the slot offsets.  Slots
+// hold an event's holes, then its electrons; within each species the slots
+// of a multi-deposit event run deposit-major (deposit_major).  Outputs are
+// indexed by carrier.
 __global__ __launch_bounds__(256) void k_seed(DevParams dp, DevBatch bt)
 {
     const int g = blockIdx.x * 256 + threadIdx.x;
@@ -989,10 +1010,13 @@ __global__ __launch_bounds__(256) void k_seed(DevParams dp, DevBatch bt)
         else hi = mid;
     }
     const int b = lo;
-    const int k = g - bt.off[b];
-    const bool electron = k >= bt.nh0[b];
-    double x, y, z;
+    const int s = g - bt.off[b];
+    const int nh = bt.nh0[b], n = bt.off[b + 1] - bt.off[b];
     const int d0 = bt.dep_off[b], nd = bt.dep_off[b + 1] - d0;
+    const int k = s < nh ? deposit_major(s, nh, nd) : nh + deposit_major(s - nh, n - nh, nd);
+    const int carrier = bt.off[b] + k;
+    const bool electron = k >= nh;
+    double x, y, z;
     if (nd > 0) {
         // electron k of a cloud event starts where hole k starts: same draw
         const int kh = electron ? k - bt.nh0[b] : k;
@@ -1016,8 +1040,8 @@ __global__ __launch_bounds__(256) void k_seed(DevParams dp, DevBatch bt)
     bt.nx[g] = x;
     bt.ny[g] = y;
     bt.nz[g] = z;
-    bt.out_cstep[g] = -1;
-    if (done) collect(dp, bt, b, g, electron, x, y, z, bt.start[b]);
+    bt.out_cstep[carrier] = -1;
+    if (done) collect(dp, bt, b, carrier, electron, x, y, z, bt.start[b]);
 }
 
 // Current positions of drifting carriers into the carrier-ordered output.

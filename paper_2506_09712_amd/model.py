@@ -106,8 +106,9 @@ def parameterise(sensor, energy_kev: float, depths: Sequence[float], repeats: in
                  precision: int = 1, sigma_um: float = -1.0, beta_p0=(0.5, -0.5, -0.8, -0.5, -1.0),
                  device: int = 0) -> dict:
     """Simulate `repeats` events of energy_kev at each absorption depth (um
-    from the entrance side) with the library, fit the GGD to the collected
-    holes' x and y (pooled, relative to the absorption point) at each depth,
+    from the entrance side) with the library (holes, or holes and electrons
+    when the sensor simulates both), fit the GGD to the collected holes' x
+    and y (pooled, relative to the absorption point) at each depth,
     then Eqs. 10 and 11 over the drift times of Eq. 9 (with at least five
     depths; else p_alpha and p_beta are None).  The initial cloud width is
     Eq. 2 unless sigma_um >= 0."""
@@ -125,10 +126,13 @@ def parameterise(sensor, energy_kev: float, depths: Sequence[float], repeats: in
     with binding.Simulator(sensor, precision, device=device) as sim:
         r = sim.run(batch)
     off = r["offsets"]
+    # each event's rows hold its holes, then (two species) as many electrons
+    n_holes = (off[1:] - off[:-1]) // (2 if sensor.electrons else 1)
     alpha, beta = np.zeros(len(depths)), np.zeros(len(depths))
     for i in range(len(depths)):
-        sl = slice(off[i * repeats], off[(i + 1) * repeats])
-        xy = r["xyz"][sl, :2].reshape(-1)
+        rows = [r["xyz"][off[e]:off[e] + n_holes[e], :2]
+                for e in range(i * repeats, (i + 1) * repeats)]
+        xy = np.concatenate(rows).reshape(-1)
         alpha[i], beta[i] = ggd_mle(xy)
     t = drift_time(sensor, depths)
     # Eq. 11 has five parameters: fit the parameterisation from five depths up

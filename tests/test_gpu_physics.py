@@ -36,13 +36,16 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def test_ggd_beta_at_the_paper_depths():
+@pytest.mark.parametrize("electrons", [False, True], ids=["holes", "holes_and_electrons"])
+def test_ggd_beta_at_the_paper_depths(electrons):
+    """Sec. 2.1 simulates electrons and holes; the fit is to the holes."""
     ref = json.load(open(os.path.join(HERE, "golden", "paper_ggd_beta.json")))
     s = Sensor(thickness_um=320.0, v_bias=150.0, v_dep=29.6, temperature_k=273.15 + 34.7,
-               dt_ns=0.01, pair_energy_ev=3.62, seed=0)
+               dt_ns=0.01, pair_energy_ev=3.62, seed=0, electrons=electrons)
     r = model.parameterise(s, 25.0, ref["depth_um"], repeats=10, precision=1)
     beta = r["beta"]
-    print("fitted beta", beta, "paper", ref["beta"], "alpha", r["alpha"])
+    print("electrons" if electrons else "holes", "fitted beta", beta, "paper", ref["beta"],
+          "alpha", r["alpha"])
     np.testing.assert_allclose(beta, ref["beta"], rtol=0, atol=0.1)
     assert beta[0] > beta[1] > beta[2] > 2.0
 

@@ -39,9 +39,12 @@ def test_mixed_field_matches_oracle(ct, nh, ne, prec):
     xyz = np.concatenate([h, e])
     q = np.concatenate([np.ones(nh), -np.ones(ne)])
     ref = oracle.field_q(s, xyz, q)
-    bound = field_error_bound(xyz, s.softening_um, oracle.coulomb_k(s), prec == FP32)
     b = explicit_batch([h], electrons_per_event=[e])
     for launch in [None, (1, 128, 128), (2, 256, 256), (1, 64, 64)]:
+        # the tile of an item's targets (the frame of its FP32 coordinates)
+        frame = 256 if launch is None or prec == FP64 else launch[0] * launch[1]
+        bound = field_error_bound(xyz, s.softening_um, oracle.coulomb_k(s), prec == FP32,
+                                  frame_tile=frame)
         with ct.Simulator(s, prec, launch=launch) as sim:
             sim.seed(b)
             E = sim.field()

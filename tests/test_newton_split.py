@@ -85,3 +85,45 @@ def test_newton_split_meets_every_pair_once(tmp_path):
                    check=True, capture_output=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and "split ok" in r.stdout, r.stdout + r.stderr
+
+
+ORDER_PROGRAM = r"""
+#include "ct_internal.hpp"
+#include <cstdio>
+#include <vector>
+
+// deposit_major must be a bijection of [0, n) whose slots run deposit by
+// deposit (carrier k on deposit k mod nd), each deposit's carriers in
+// increasing order.
+int main()
+{
+    for (int nd : {0, 1, 2, 3, 7, 40, 41, 100})
+        for (int n : {0, 1, 2, 5, 39, 40, 41, 79, 80, 81, 1389, 55556, 55557}) {
+            std::vector<int> seen(n > 0 ? n : 1, 0);
+            int prev_d = -1, prev_k = -1;
+            for (int s = 0; s < n; ++s) {
+                const int k = ct::deposit_major(s, n, nd);
+                if (k < 0 || k >= n || seen[k]++) { std::printf("nd %d n %d s %d: k %d\n", nd, n, s, k); return 1; }
+                if (nd <= 1) { if (k != s) return 2; continue; }
+                const int d = k % nd;
+                if (d < prev_d || (d == prev_d && k <= prev_k)) { std::printf("order nd %d n %d s %d\n", nd, n, s); return 3; }
+                prev_d = d;
+                prev_k = k;
+            }
+        }
+    std::puts("order ok");
+    return 0;
+}
+"""
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc is not installed")
+def test_deposit_major_slot_order_is_a_bijection(tmp_path):
+    src = tmp_path / "order.hip"
+    src.write_text(ORDER_PROGRAM)
+    exe = tmp_path / "order"
+    subprocess.run([HIPCC, "-std=c++17", "-O2", "--offload-arch=gfx950", "-I", CSRC,
+                    "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "order ok" in r.stdout, r.stdout + r.stderr
