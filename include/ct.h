@@ -214,6 +214,34 @@ ct_status ct_bind_workspace(ct_ctx *c, void *device_ptr, size_t bytes);
 ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
                          uint64_t first_event_id);
 
+/* ct_seed_events for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same seeding and the same results, with no hipMalloc or hipFree.
+ *   - The batch lives in the workspace the caller bound with
+ *     ct_bind_workspace (at least ct_workspace_bytes for the batch); a context
+ *     that ever let the library allocate a batch workspace is refused
+ *     (CT_ESTATE), as are contexts without a bound workspace (CT_ESTATE) and
+ *     CT_OPT_AUTOTUNE (CT_EINVAL: the tuner allocates).
+ *   - The batch's work queue, partial fields and counters go to one static
+ *     array of 128 MiB per GPU that the library holds until the process
+ *     ends.  A batch whose queue does not fit it even at one step's worth of
+ *     work items is refused with CT_ENOMEM, before the context changes (with
+ *     the default FP32 launch the 256 events of 2222 holes of the 8 keV batch
+ *     fit, or 7 events of 16,667 holes; the Newton-pair partial fields of one
+ *     55,556-hole event, 175 MB, do not); a queue shorter than
+ *     ct_seed_events' parks more events, which ct_step runs again (same
+ *     results, more launches).
+ *   - Every context on a GPU shares that GPU's array, which keeps the last
+ *     user's contents (this call clears what must start at zero).  Seeding
+ *     another context with this call on the same GPU takes the array over;
+ *     ct_step, ct_collect, ct_field and ct_set_launch of the earlier context
+ *     then return CT_ESTATE until it is seeded again.  Calls on contexts that
+ *     share a GPU's array must not overlap in time: they race on it.
+ * ct_step and ct_collect allocate nothing in any case; ct_field allocates its
+ * output staging on first use. */
+ct_status ct_seed_events_noalloc(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
+                                 uint64_t first_event_id);
+
 /* The time-step loop of Algorithm 1 (Appendix A): while an event has holes
  * drifting, evaluate the field of Eq. 4 at every drifting carrier from the
  * step-start positions, then move each carrier by Eqs. 3, 5 and 6 and

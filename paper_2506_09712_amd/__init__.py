@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     CT_OPT_TIMING,
     CT_REPULSION, CT_SPHERICAL, CtError, EXPORTS, ct_generate, generate, make_gen_params,
     Simulator, ct_bind_workspace, ct_collect, ct_destroy, ct_event_carriers, ct_field,
-    ct_init_sensor, ct_philox, ct_seed_events, ct_set_launch, ct_step, ct_workspace_bytes, load,
+    ct_init_sensor, ct_philox, ct_seed_events, ct_seed_events_noalloc, ct_set_launch, ct_step,
+    ct_workspace_bytes, load,
     make_params, EventDescs, run,
 )

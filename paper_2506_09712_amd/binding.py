@@ -87,7 +87,7 @@ class ct_run_stats(C.Structure):
 
 
 EXPORTS = ["ct_init_sensor", "ct_event_carriers", "ct_workspace_bytes", "ct_bind_workspace",
-           "ct_seed_events", "ct_step", "ct_collect", "ct_field", "ct_philox", "ct_set_launch",
+           "ct_seed_events", "ct_seed_events_noalloc", "ct_step", "ct_collect", "ct_field", "ct_philox", "ct_set_launch",
            "ct_destroy", "ct_last_error", "ct_generate"]
 
 _lib = None
@@ -113,6 +113,8 @@ def load(path: str = LIB_PATH):
     L.ct_bind_workspace.restype = st
     L.ct_seed_events.argtypes = [C.c_void_p, P(ct_event_desc), C.c_int32, C.c_uint64]
     L.ct_seed_events.restype = st
+    L.ct_seed_events_noalloc.argtypes = [C.c_void_p, P(ct_event_desc), C.c_int32, C.c_uint64]
+    L.ct_seed_events_noalloc.restype = st
     L.ct_step.argtypes = [C.c_void_p, C.c_int64, P(C.c_int64), P(C.c_int64)]
     L.ct_step.restype = st
     L.ct_collect.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_double), P(C.c_int32), P(C.c_int64),
@@ -216,6 +218,11 @@ def ct_bind_workspace(ctx, ptr: Optional[int], nbytes: int) -> None:
 
 def ct_seed_events(ctx, descs: EventDescs, first_event_id: int = 0) -> None:
     _check(load().ct_seed_events(ctx, descs.arr, descs.n, int(first_event_id)), "ct_seed_events")
+
+
+def ct_seed_events_noalloc(ctx, descs: EventDescs, first_event_id: int = 0) -> None:
+    _check(load().ct_seed_events_noalloc(ctx, descs.arr, descs.n, int(first_event_id)),
+           "ct_seed_events_noalloc")
 
 
 def ct_step(ctx, max_steps: int = 0):
@@ -369,7 +376,7 @@ class Simulator:
     def set_launch(self, targets_per_thread=0, block_size=0, chunk_len=0):
         ct_set_launch(self.ctx, targets_per_thread, block_size, chunk_len)
 
-    def seed(self, batch, ids=None):
+    def seed(self, batch, ids=None, noalloc: bool = False):
         if ids is None and self._descs is not None and self._descs_of is batch:
             descs = self._descs  # same batch object: reuse its marshalled descriptions
         else:
@@ -381,7 +388,7 @@ class Simulator:
                 ct_bind_workspace(self.ctx, None, 0)
                 self._ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.params.device}")
             ct_bind_workspace(self.ctx, self._ws.data_ptr(), self._ws.numel())
-        ct_seed_events(self.ctx, descs, batch.first_event_id)
+        (ct_seed_events_noalloc if noalloc else ct_seed_events)(self.ctx, descs, batch.first_event_id)
         self.batch = batch
         self.n_total = int(self.counts.sum())
         self._descs = descs

@@ -295,7 +295,7 @@ struct QueueLayout {
 // its tickets (one per workgroup of each event; sph_max_group bounds the
 // workgroups sharing an event) and the state of shared events.
 QueueLayout make_queue_layout(const BatchShape &s, const ct::LaunchCfg &cfg, bool repulsion,
-                              bool spherical, int sph_max_group)
+                              bool spherical, int sph_max_group, int64_t cap_max = kQueueMax)
 {
     QueueLayout Q{};
     const int64_t T = (int64_t)cfg.kt * cfg.bs;
@@ -334,7 +334,8 @@ QueueLayout make_queue_layout(const BatchShape &s, const ct::LaunchCfg &cfg, boo
         if (G == 1) Q.single_h.push_back((int32_t)b);
     }
     Q.n_tickets = Q.tk_off_h[s.B];
-    int64_t cap = std::max<int64_t>(items, std::min<int64_t>(items * queue_steps(), kQueueMax));
+    int64_t cap = std::max<int64_t>(items, std::min<int64_t>(items * queue_steps(),
+                                                             std::min(kQueueMax, cap_max)));
     cap = std::max<int64_t>(cap, 1);
     Q.cap = (uint32_t)cap;
     size_t o = 0;
@@ -385,6 +386,7 @@ struct ct_ctx {
     void *qbuf = nullptr;
     size_t qbuf_bytes = 0;
     ct::DevQueue dq{};
+    bool in_scratch = false;  // the queue lives in the device's shared scratch (ct_seed_events_noalloc)
     uint32_t gen = 0;
     bool broken = false;  // a run reported an error; only ct_destroy is allowed
 
@@ -452,6 +454,39 @@ ct_status set_device(ct_ctx *c)
     return CT_OK;
 }
 
+// The context whose batch queue occupies each device's scratch (seeded with
+// ct_seed_events_noalloc).  A later such seeding on the same device takes the
+// scratch over; the earlier context's calls then fail with CT_ESTATE instead
+// of running on a queue that is no longer its own.
+std::mutex g_owner_mu;
+std::map<int, const ct_ctx *> g_owner;
+
+void claim_scratch(const ct_ctx *c)
+{
+    std::lock_guard<std::mutex> lk(g_owner_mu);
+    g_owner[c->device] = c;
+}
+
+void release_scratch(const ct_ctx *c)
+{
+    std::lock_guard<std::mutex> lk(g_owner_mu);
+    auto it = g_owner.find(c->device);
+    if (it != g_owner.end() && it->second == c) g_owner.erase(it);
+}
+
+// CT_OK unless the context's queue was in the scratch and another context
+// has taken the scratch over since.
+ct_status check_scratch(const ct_ctx *c)
+{
+    if (!c->seeded || !c->in_scratch) return CT_OK;
+    std::lock_guard<std::mutex> lk(g_owner_mu);
+    auto it = g_owner.find(c->device);
+    if (it == g_owner.end() || it->second != c)
+        return fail(CT_ESTATE, "the scratch of device %d now holds another context's batch "
+                               "(ct_seed_events_noalloc); seed this context again", c->device);
+    return CT_OK;
+}
+
 // Work queue of the seeded batch for cfg, and the resident grid.  The queue
 // memory is kept while it is large enough; its sequence words are cleared
 // whenever it is (re)allocated, so no stale ticket can match a generation.
@@ -483,7 +518,28 @@ ct_status prepare_queue(ct_ctx *c, const ct::LaunchCfg &cfg_in)
     }
     QueueLayout Q = make_queue_layout(c->shape, cfg, repulsion, spherical, sph_cap);
     hipStream_t sm = c->stream;
-    if (Q.total > c->qbuf_bytes) {
+    void *qmem = nullptr;
+    if (c->in_scratch) {
+        // the device's shared scratch: no allocation.  A queue of fewer
+        // tickets than usual parks more events (run again by ct_step, same
+        // results); everything is cleared, since the array keeps the
+        // contents of the last context that used it.
+        size_t sbytes = 0;
+        CT_HIP(ct::scratch_memory(c->device, &qmem, &sbytes));
+        if (Q.total > sbytes) {
+            const QueueLayout Qmin = make_queue_layout(c->shape, cfg, repulsion, spherical, sph_cap, 1);
+            if (Qmin.total > sbytes)
+                return fail(CT_ENOMEM, "the batch's work queue needs %zu bytes; the scratch of "
+                                       "ct_seed_events_noalloc has %zu", Qmin.total, sbytes);
+            const int64_t per = sizeof(ct::QItem) + sizeof(uint32_t);
+            int64_t cap = (int64_t)Qmin.cap + (int64_t)(sbytes - Qmin.total) / per;
+            do {
+                Q = make_queue_layout(c->shape, cfg, repulsion, spherical, sph_cap, cap);
+                cap -= 64;
+            } while (Q.total > sbytes);
+        }
+        CT_HIP(ct::launch_fill_i32((int32_t *)qmem, (int64_t)(Q.total / 4), 0, sm));
+    } else if (Q.total > c->qbuf_bytes) {
         if (c->qbuf) {
             CT_HIP(hipStreamSynchronize(sm));
             CT_HIP(hipFree(c->qbuf));
@@ -497,25 +553,27 @@ ct_status prepare_queue(ct_ctx *c, const ct::LaunchCfg &cfg_in)
         }
         c->qbuf_bytes = Q.total;
         CT_HIP(ct::launch_fill_i32((int32_t *)c->qbuf, (int64_t)(c->qbuf_bytes / 4), 0, sm));
+        qmem = c->qbuf;
     } else {
         // the sequence words move with the layout: clear them for this one
         CT_HIP(ct::launch_fill_i32(at<int32_t>(c->qbuf, Q.seq), (int64_t)Q.cap, 0, sm));
+        qmem = c->qbuf;
     }
     ct::DevQueue d{};
-    d.sc = at<ct::Sched>(c->qbuf, Q.sched);
-    d.q = at<ct::QItem>(c->qbuf, Q.q);
-    d.seq = at<uint32_t>(c->qbuf, Q.seq);
+    d.sc = at<ct::Sched>(qmem, Q.sched);
+    d.q = at<ct::QItem>(qmem, Q.q);
+    d.seq = at<uint32_t>(qmem, Q.seq);
     d.cap = Q.cap;
-    d.tiles_left = at<int32_t>(c->qbuf, Q.tiles_left);
-    d.chunks_left = at<int32_t>(c->qbuf, Q.chunks_left);
-    d.tile_base = at<int32_t>(c->qbuf, Q.tile_base);
-    d.part = at<double>(c->qbuf, Q.part);
-    d.part_off = at<int64_t>(c->qbuf, Q.part_off);
-    d.tk_off = at<int32_t>(c->qbuf, Q.tk_off);
-    d.grp_off = at<int64_t>(c->qbuf, Q.grp_off);
-    d.grp = at<char>(c->qbuf, Q.grp);
+    d.tiles_left = at<int32_t>(qmem, Q.tiles_left);
+    d.chunks_left = at<int32_t>(qmem, Q.chunks_left);
+    d.tile_base = at<int32_t>(qmem, Q.tile_base);
+    d.part = at<double>(qmem, Q.part);
+    d.part_off = at<int64_t>(qmem, Q.part_off);
+    d.tk_off = at<int32_t>(qmem, Q.tk_off);
+    d.grp_off = at<int64_t>(qmem, Q.grp_off);
+    d.grp = at<char>(qmem, Q.grp);
     d.n_tickets = Q.n_tickets;
-    d.single = at<int32_t>(c->qbuf, Q.single);
+    d.single = at<int32_t>(qmem, Q.single);
     if (c->shape.B > 0) {
         CT_HIP(hipMemcpyAsync((void *)d.tile_base, Q.tile_base_h.data(),
                               sizeof(int32_t) * (c->shape.B + 1), hipMemcpyHostToDevice, sm));
@@ -810,7 +868,9 @@ ct_status ct_set_launch(ct_ctx *c, int32_t kt, int32_t bs, int32_t chunk_len)
         return fail(CT_EINVAL, "chunk_len %d must be a multiple of the block size %d, at most 2^20",
                     n.chunk, n.bs);
     if (c->seeded) {
-        ct_status st = set_device(c);
+        ct_status st = check_scratch(c);
+        if (st != CT_OK) return st;
+        st = set_device(c);
         if (st != CT_OK) return st;
         st = prepare_queue(c, n);
         if (st != CT_OK) return st;
@@ -819,8 +879,38 @@ ct_status ct_set_launch(ct_ctx *c, int32_t kt, int32_t bs, int32_t chunk_len)
     return CT_OK;
 }
 
-ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
-                         uint64_t first_event_id)
+}  // extern "C"
+
+namespace {
+
+// The work queue of a batch of this shape fits the device's scratch (at the
+// smallest ticket count that still holds one step of every event).
+ct_status scratch_fits(ct_ctx *c, const BatchShape &s)
+{
+    void *mem = nullptr;
+    size_t bytes = 0;
+    CT_HIP(ct::scratch_memory(c->device, &mem, &bytes));
+    const bool spherical = (c->p.physics_flags & CT_SPHERICAL) != 0;
+    int sph_cap = 0;
+    if (spherical) {
+        const int occ = ct::sph_occupancy();
+        if (occ <= 0) return fail(CT_EDEVICE, "spherical kernel occupancy query failed");
+        sph_cap = occ * c->cu_count;
+    }
+    const QueueLayout Q = make_queue_layout(s, resolve_cfg(c, c->cfg),
+                                            (c->p.physics_flags & CT_REPULSION) != 0, spherical,
+                                            sph_cap, 1);
+    if (Q.total > bytes)
+        return fail(CT_ENOMEM, "the batch's work queue needs %zu bytes; the scratch of "
+                               "ct_seed_events_noalloc has %zu", Q.total, bytes);
+    return CT_OK;
+}
+
+// ct_seed_events and ct_seed_events_noalloc: the batch goes to the context's
+// workspace (allocated, or bound by the caller), its work queue to the
+// context's own allocation or, with noalloc, to the device's scratch.
+ct_status seed(ct_ctx *c, const ct_event_desc *ev, int32_t n_events, uint64_t first_event_id,
+               bool noalloc)
 {
     if (!c) return fail(CT_EINVAL, "ctx is NULL");
     if (c->broken) return fail(CT_EDEVICE, "context unusable after a device error");
@@ -828,6 +918,31 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     ct_status st = shape_of(c->p, ev, n_events, s);
     if (st != CT_OK) return st;
     if (s.B > 65535) return fail(CT_EINVAL, "at most 65535 events per batch");
+    if (noalloc) {
+        if (c->p.options & CT_OPT_AUTOTUNE)
+            return fail(CT_EINVAL, "ct_seed_events_noalloc does not autotune (the tuner allocates)");
+        if (!c->bound_ptr)
+            return fail(CT_ESTATE, "ct_seed_events_noalloc needs a workspace bound with "
+                                   "ct_bind_workspace");
+        if (c->ws && !c->ws_bound)
+            return fail(CT_ESTATE, "the context holds a batch workspace the library allocated; "
+                                   "ct_seed_events_noalloc needs a context that never allocated one");
+        const size_t need = make_layout(s.B, s.N, s.n_dep, s.n_exp, c->p.grid_n * c->p.grid_n + 1,
+                                        (c->p.physics_flags & CT_SPHERICAL) != 0)
+                                .total;
+        if (c->bound_bytes < need)
+            return fail(CT_ENOMEM, "bound workspace has %zu bytes, batch needs %zu", c->bound_bytes,
+                        need);
+        st = set_device(c);
+        if (st != CT_OK) return st;
+        st = scratch_fits(c, s);
+        if (st != CT_OK) return st;
+        c->in_scratch = true;
+        claim_scratch(c);
+    } else if (c->in_scratch) {
+        release_scratch(c);
+        c->in_scratch = false;
+    }
     // host-side staging of the event descriptions
     const int G1 = c->p.grid_n * c->p.grid_n + 1;
     std::vector<int32_t> off(s.B + 1), dep_off(s.B + 1), x_off(s.B + 1), rngid(s.N);
@@ -942,12 +1057,28 @@ ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
     c->field_ms = 0.0;
     c->step_wall_ms = 0.0;
     c->seeded = true;
-    if ((c->p.options & CT_OPT_AUTOTUNE) && (c->p.physics_flags & CT_REPULSION) && s.N > 0 &&
-        !spherical(c)) {
+    if (!noalloc && (c->p.options & CT_OPT_AUTOTUNE) && (c->p.physics_flags & CT_REPULSION) &&
+        s.N > 0 && !spherical(c)) {
         st = autotune(c);
         if (st != CT_OK) return st;
     }
     return CT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ct_status ct_seed_events(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
+                         uint64_t first_event_id)
+{
+    return seed(c, ev, n_events, first_event_id, false);
+}
+
+ct_status ct_seed_events_noalloc(ct_ctx *c, const ct_event_desc *ev, int32_t n_events,
+                                 uint64_t first_event_id)
+{
+    return seed(c, ev, n_events, first_event_id, true);
 }
 
 ct_status ct_step(ct_ctx *c, int64_t max_steps, int64_t *steps_done, int64_t *n_active)
@@ -955,7 +1086,9 @@ ct_status ct_step(ct_ctx *c, int64_t max_steps, int64_t *steps_done, int64_t *n_
     if (!c) return fail(CT_EINVAL, "ctx is NULL");
     if (c->broken) return fail(CT_EDEVICE, "context unusable after a device error");
     if (!c->seeded) return fail(CT_ESTATE, "ct_step before ct_seed_events");
-    ct_status st = set_device(c);
+    ct_status st = check_scratch(c);
+    if (st != CT_OK) return st;
+    st = set_device(c);
     if (st != CT_OK) return st;
     if (max_steps <= 0) max_steps = c->p.max_steps;
     const auto t_start = std::chrono::steady_clock::now();
@@ -995,7 +1128,9 @@ ct_status ct_collect(ct_ctx *c, int32_t *pixel_counts, double *xyz, int32_t *col
     if (!c) return fail(CT_EINVAL, "ctx is NULL");
     if (c->broken) return fail(CT_EDEVICE, "context unusable after a device error");
     if (!c->seeded) return fail(CT_ESTATE, "ct_collect before ct_seed_events");
-    ct_status st = set_device(c);
+    ct_status st = check_scratch(c);
+    if (st != CT_OK) return st;
+    st = set_device(c);
     if (st != CT_OK) return st;
     const int64_t B = c->shape.B, N = c->shape.N;
     const int G1 = c->p.grid_n * c->p.grid_n + 1;
@@ -1046,7 +1181,9 @@ ct_status ct_field(ct_ctx *c, double *field)
     if (c->broken) return fail(CT_EDEVICE, "context unusable after a device error");
     if (!c->seeded) return fail(CT_ESTATE, "ct_field before ct_seed_events");
     if (!field) return fail(CT_EINVAL, "field is NULL");
-    ct_status st = set_device(c);
+    ct_status st = check_scratch(c);
+    if (st != CT_OK) return st;
+    st = set_device(c);
     if (st != CT_OK) return st;
     const int64_t N = c->shape.N;
     if (N == 0) return CT_OK;
@@ -1165,6 +1302,7 @@ ct_status ct_generate(ct_ctx *c, const ct_gen_params *g, int64_t n_events,
 void ct_destroy(ct_ctx *c)
 {
     if (!c) return;
+    release_scratch(c);
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->ws && !c->ws_bound) (void)hipFree(c->ws);

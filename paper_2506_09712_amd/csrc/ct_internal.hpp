@@ -168,6 +168,10 @@ uint64_t run_idle_ticks();
 hipError_t launch_gen(const GenDev &g, int64_t n_events, double *energy, int32_t *counts,
                       double *info, hipStream_t s);
 int run_occupancy(const LaunchCfg &cfg, int fp32);
+// The device address and size of the library's static scratch array on a
+// device (for contexts seeded with ct_seed_events_noalloc); the device must
+// be current.  Looked up once per device.
+hipError_t scratch_memory(int device, void **ptr, size_t *bytes);
 bool launch_supported(int kt, int bs);
 hipError_t launch_scatter_alive(const DevBatch &bt, int n_max, hipStream_t s);
 hipError_t launch_philox(const DevParams &dp, const uint32_t *ctr, int64_t n, uint32_t *words,

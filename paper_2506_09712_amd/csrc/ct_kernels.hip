@@ -21,6 +21,8 @@
 // The split of an event into tiles and chunks depends only on its own hole
 // count, and partials are always summed in chunk order, so the result of an
 // event does not depend on the rest of the batch or on scheduling.
+#include <mutex>
+
 #include "ct_device.hpp"
 
 namespace ct {
@@ -1132,7 +1134,41 @@ uint64_t idle_ticks()
 
 }  // namespace
 
+// ---------------------------------------- memory for callers that cannot allocate
+
+// Work queue, partial fields and counters of contexts seeded with
+// ct_seed_events_noalloc: one array per GPU, held from the library's load
+// until the process ends, shared by every such context on that GPU.  In host
+// code its name is only a stand-in: the device address comes from
+// hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+}  // namespace
+
 // ------------------------------------------------------------------ launchers
+
+hipError_t scratch_memory(int device, void **ptr, size_t *bytes)
+{
+    *ptr = nullptr;
+    *bytes = 0;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        // with that device current (the caller has set it)
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    *bytes = kScratchBytes;
+    return hipSuccess;
+}
 
 uint64_t run_idle_ticks() { return idle_ticks(); }
 
