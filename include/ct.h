@@ -104,10 +104,19 @@ enum { CT_REPULSION = 1u, CT_DRIFT = 2u, CT_DIFFUSION = 4u, CT_ELECTRONS = 8u, C
 /* options bits */
 enum {
     CT_OPT_TIMING = 1u,   /* time every run of the step kernel with HIP events (ct_run_stats) */
-    CT_OPT_AUTOTUNE = 4u, /* on seeding, time the launch configurations on one field evaluation
-                             of the seeded state and keep the fastest (cached per precision and
-                             batch-shape bucket); the chosen configuration sets the grouping of
-                             the field sum (see ct_set_launch) */
+    CT_OPT_AUTOTUNE = 4u, /* on seeding, time candidate launch configurations on the first
+                             steps of the seeded batch (environment variable CT_TUNE_STEPS, by
+                             default as many as make about 2e10 pair evaluations, 2 to 32; each
+                             from the freshly seeded state, the persistent kernel alone) and
+                             keep the fastest; candidates keep Newton pairs
+                             where the context uses them.  The choice is cached per device
+                             architecture, compute units, precision, physics switches,
+                             CT_OPT_ONE_SIDED and batch shape (events, largest event, total
+                             carriers, in powers of two), in memory and in the file
+                             CT_TUNE_CACHE (default $XDG_CACHE_HOME or ~/.cache
+                             /ct_launch_cache.txt), so later processes reuse it.  The batch is
+                             left as seeded.  The chosen configuration sets the grouping of the
+                             field sum (see ct_set_launch) */
     CT_OPT_ONE_SIDED = 8u /* CT_FP32: evaluate every ordered pair (i, j) on its own.  By default
                              an FP32 run with one target per thread and blocks of 256
                              evaluates each unordered pair once and applies it to both carriers

@@ -17,6 +17,8 @@
 #include <tuple>
 #include <vector>
 
+#include <sys/stat.h>
+
 #include "ct.h"
 #include "ct_internal.hpp"
 #include "ct_sph_layout.hpp"
@@ -370,6 +372,7 @@ struct ct_ctx {
     bool own_stream = false;
     ct::LaunchCfg cfg{1, 256, 1280};
     int cu_count = 0;
+    std::string arch;  // gcnArchName of the device
     int grid = 0;  // resident workgroups of the run kernel for cfg
     int grid_shared = 0;  // spherical model: workgroups over the events shared by several
 
@@ -395,6 +398,7 @@ struct ct_ctx {
     Layout L{};
     ct::DevBatch bt{};
     BatchShape shape;
+    std::vector<int64_t> start_h;  // start step of each event (host copy, for re-seeding)
     int64_t n_active = 0;
     int64_t steps = 0;
 
@@ -693,11 +697,17 @@ ct_status field_into_buf(ct_ctx *c, const ct::LaunchCfg &cfg, bool timing)
     return run_once(c, cfg, INT64_MAX, 1, c->field_buf, timing);
 }
 
-// Launch configurations chosen by the autotuner, per precision, device and
-// batch shape bucket (events, largest event, total holes; powers of two).
-using TuneKey = std::tuple<int, int, int, int, int>;
-std::map<TuneKey, ct::LaunchCfg> g_tuned;
+ct_status reset_state(ct_ctx *c);
+
+// Launch configurations chosen by the autotuner.  Key: device architecture,
+// compute units, precision, physics switches, options that change the
+// kernel, and the batch shape in powers of two (events, largest event, total
+// carriers).  Kept in memory and in a text file (CT_TUNE_CACHE, default
+// $XDG_CACHE_HOME or ~/.cache /ct_launch_cache.txt; one "key|kt bs chunk"
+// line per entry), so that later processes reuse it.
+std::map<std::string, ct::LaunchCfg> g_tuned;
 std::mutex g_tuned_mu;
+bool g_tuned_loaded = false;
 
 int log2_bucket(int64_t v)
 {
@@ -709,17 +719,93 @@ int log2_bucket(int64_t v)
     return b;
 }
 
-// Time one field evaluation of the seeded state per candidate and keep the
-// fastest.  The state is not advanced.
+std::string tune_cache_path()
+{
+    if (const char *v = std::getenv("CT_TUNE_CACHE")) return v;
+    std::string dir;
+    if (const char *x = std::getenv("XDG_CACHE_HOME")) dir = x;
+    else if (const char *h = std::getenv("HOME")) dir = std::string(h) + "/.cache";
+    else return "";
+    return dir + "/ct_launch_cache.txt";
+}
+
+void load_tune_cache()  // g_tuned_mu held
+{
+    if (g_tuned_loaded) return;
+    g_tuned_loaded = true;
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char *bar = std::strchr(line, '|');
+        if (!bar) continue;
+        *bar = 0;
+        ct::LaunchCfg cfg{};
+        if (std::sscanf(bar + 1, "%d %d %d", &cfg.kt, &cfg.bs, &cfg.chunk) == 3 &&
+            ct::launch_supported(cfg.kt, cfg.bs) && cfg.chunk >= cfg.bs && cfg.chunk % cfg.bs == 0)
+            g_tuned[line] = cfg;
+    }
+    std::fclose(f);
+}
+
+void store_tune_cache(const std::string &key, const ct::LaunchCfg &cfg)  // g_tuned_mu held
+{
+    g_tuned[key] = cfg;
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        const std::string dir = path.substr(0, slash);
+        std::string acc;
+        for (size_t i = 0; i <= dir.size(); ++i)
+            if (i == dir.size() || (dir[i] == '/' && i > 0)) {
+                acc = dir.substr(0, i);
+                (void)mkdir(acc.c_str(), 0755);
+            }
+    }
+    if (FILE *f = std::fopen(path.c_str(), "a")) {  // one short line per append
+        std::fprintf(f, "%s|%d %d %d\n", key.c_str(), cfg.kt, cfg.bs, cfg.chunk);
+        std::fclose(f);
+    }
+}
+
+// Steps of the whole-run prefix each candidate is timed on: CT_TUNE_STEPS,
+// else enough for about 2e10 pair evaluations (the first step's pairs set
+// the pace), between 2 and 32.
+int64_t tune_steps(const BatchShape &s)
+{
+    const char *v = std::getenv("CT_TUNE_STEPS");
+    const long long k = v ? std::atoll(v) : 0;
+    if (k >= 1) return (int64_t)k;
+    double pairs = 0.0;
+    for (int32_t n : s.n) pairs += (double)n * (double)n;
+    const double steps = pairs > 0.0 ? 2e10 / pairs : 32.0;
+    return (int64_t)std::max(2.0, std::min(32.0, std::floor(steps)));
+}
+
+// Time the first tune_steps() steps of the seeded batch under each candidate
+// launch (the persistent kernel only, HIP events; the better of two runs,
+// each from the freshly seeded state) and keep the fastest.  Every candidate
+// runs the same steps of the same events, so the fastest prefix is the one
+// with the highest pair rate.  Candidates keep Newton pairs where the context
+// uses them (FP32, repulsion, CT_OPT_ONE_SIDED unset): one target per thread,
+// blocks of 256, chunks of 1 to 15 tiles.  The state is the seeded one
+// afterwards.
 ct_status autotune(ct_ctx *c)
 {
-    const int fp32 = c->p.precision == CT_FP32;
-    const TuneKey key{fp32, c->device, log2_bucket(c->shape.B), log2_bucket(c->shape.n_max),
-                      log2_bucket(c->shape.N)};
+    const bool newton = resolve_cfg(c, ct::LaunchCfg{1, ct::kSymTile, ct::kSymTile}).newton != 0;
+    char key[256];
+    std::snprintf(key, sizeof key, "%s cu%d p%d f%u o%u B%d n%d N%d", c->arch.c_str(), c->cu_count,
+                  (int)c->p.precision, (unsigned)c->p.physics_flags,
+                  (unsigned)(c->p.options & CT_OPT_ONE_SIDED), log2_bucket(c->shape.B),
+                  log2_bucket(c->shape.n_max), log2_bucket(c->shape.N));
     ct::LaunchCfg best = c->cfg;
     bool cached = false;
     {
         std::lock_guard<std::mutex> lk(g_tuned_mu);
+        load_tune_cache();
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) {
             best = it->second;
@@ -728,40 +814,45 @@ ct_status autotune(ct_ctx *c)
     }
     ct_status st;
     if (!cached) {
-        st = ensure_field_buf(c, c->shape.N);
-        if (st != CT_OK) return st;
-        // long chunks suit large batches (fewer partial fields), short chunks
-        // and small tiles suit a few events (more work items per step)
-        const std::vector<ct::LaunchCfg> cand = {
-            {1, 256, 256},  {1, 256, 512},  {1, 256, 768},  {1, 256, 1280}, {1, 256, 1536},
-            {1, 256, 2304}, {1, 128, 256},  {1, 128, 512},  {2, 256, 1280}};
+        std::vector<ct::LaunchCfg> cand;
+        if (newton) {
+            for (int chunk : {256, 512, 768, 1024, 1280, 1792, 2304, 3840})
+                cand.push_back(ct::LaunchCfg{1, ct::kSymTile, chunk});
+        } else {
+            cand = {{1, 256, 512}, {1, 256, 768}, {1, 256, 1280}, {1, 256, 2304},
+                    {2, 256, 1280}, {1, 128, 256}, {1, 128, 512}};
+        }
+        const int64_t K = tune_steps(c->shape);
         float best_ms = 1e30f;
-        const double ms0 = c->field_ms;
-        const int64_t l0 = c->field_launches;
         for (const ct::LaunchCfg &cfg : cand) {
             st = prepare_queue(c, cfg);
             if (st != CT_OK) return st;
             float ms_min = 1e30f;
-            for (int rep = 0; rep < 3; ++rep) {
-                const double before = c->field_ms;
-                st = field_into_buf(c, cfg, true);
+            for (int rep = 0; rep < 2; ++rep) {
+                st = reset_state(c);
                 if (st != CT_OK) return st;
-                if (rep > 0) ms_min = std::min(ms_min, (float)(c->field_ms - before));
+                if (c->n_active == 0) break;
+                CT_HIP(ct::launch_fill_i32((int32_t *)c->bt.call_steps, 2 * c->shape.B, 0, c->stream));
+                const double before = c->field_ms;
+                for (;;) {  // the prefix, including any parked events
+                    st = run_once(c, cfg, K, 0, nullptr, true);
+                    if (st != CT_OK) return st;
+                    if (!c->h_sched->exhausted.v) break;
+                }
+                ms_min = std::min(ms_min, (float)(c->field_ms - before));
             }
             if (ms_min < best_ms) {
                 best_ms = ms_min;
                 best = cfg;
             }
         }
-        c->field_ms = ms0;
-        c->field_launches = l0;
         std::lock_guard<std::mutex> lk(g_tuned_mu);
-        g_tuned[key] = best;
+        store_tune_cache(key, best);
     }
     st = prepare_queue(c, best);
     if (st != CT_OK) return st;
     c->cfg = best;
-    return CT_OK;
+    return reset_state(c);
 }
 
 }  // namespace
@@ -822,6 +913,7 @@ ct_status ct_init_sensor(const ct_sensor_params *p, ct_ctx **out)
     c->device = dev;
     c->cfg = default_cfg(*p);
     c->cu_count = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
     auto bail = [&](ct_status s2) {
         ct_destroy(c);
         return s2;
@@ -903,6 +995,43 @@ ct_status scratch_fits(ct_ctx *c, const BatchShape &s)
     if (Q.total > bytes)
         return fail(CT_ENOMEM, "the batch's work queue needs %zu bytes; the scratch of "
                                "ct_seed_events_noalloc has %zu", Q.total, bytes);
+    return CT_OK;
+}
+
+// The state seeding leaves, rebuilt from the event descriptions already on
+// the device: per-event counters, the initial clouds (k_seed) and their
+// compaction.  Synchronises the context's stream.
+ct_status reset_state(ct_ctx *c)
+{
+    const BatchShape &s = c->shape;
+    const ct::DevBatch &bt = c->bt;
+    const int G1 = c->p.grid_n * c->p.grid_n + 1;
+    hipStream_t sm = c->stream;
+    auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, sm);
+    };
+    std::vector<double> ref(4 * s.B, 0.0);
+    std::vector<int64_t> zeros64(s.B, 0);
+    CT_HIP(up(bt.n_act, s.n.data(), sizeof(int32_t) * s.B));
+    CT_HIP(up(bt.n_hole, s.nh.data(), sizeof(int32_t) * s.B));
+    CT_HIP(up(bt.ev_step, c->start_h.data(), sizeof(int64_t) * s.B));
+    CT_HIP(up(bt.ev_taken, zeros64.data(), sizeof(int64_t) * s.B));
+    CT_HIP(up(bt.call_steps, zeros64.data(), sizeof(int64_t) * s.B));
+    CT_HIP(up(bt.ref, ref.data(), sizeof(double) * 4 * s.B));
+    CT_HIP(up(bt.pairs, zeros64.data(), sizeof(uint64_t) * s.B));
+    CT_HIP(up(bt.hsteps, zeros64.data(), sizeof(uint64_t) * s.B));
+    CT_HIP(ct::launch_fill_i32(bt.pix, s.B * G1, 0, sm));
+    CT_HIP(ct::launch_seed(c->dp, bt, sm));
+    CT_HIP(ct::launch_compact(c->dp, bt, sm));
+    CT_HIP(ct::launch_summary(bt, c->dq.sc, sm));
+    CT_HIP(hipMemcpyAsync(c->h_sched, c->dq.sc, sizeof(ct::Sched), hipMemcpyDeviceToHost, sm));
+    CT_HIP(hipStreamSynchronize(sm));
+    c->n_active = s.B > 0 ? c->h_sched->active : 0;
+    c->steps = 0;
+    c->field_launches = 0;
+    c->field_ms = 0.0;
+    c->step_wall_ms = 0.0;
     return CT_OK;
 }
 
@@ -1025,37 +1154,19 @@ ct_status seed(ct_ctx *c, const ct_event_desc *ev, int32_t n_events, uint64_t fi
         if (!bytes) return hipSuccess;
         return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, sm);
     };
-    std::vector<int32_t> n_act(s.n);
-    std::vector<double> ref(4 * s.B, 0.0);
-    std::vector<int64_t> zeros64(s.B, 0);
+    // the event descriptions, once; then the state every seeding starts from
     CT_HIP(up((void *)bt.off, off.data(), sizeof(int32_t) * (s.B + 1)));
-    CT_HIP(up(bt.n_act, n_act.data(), sizeof(int32_t) * s.B));
-    CT_HIP(up(bt.n_hole, s.nh.data(), sizeof(int32_t) * s.B));
     CT_HIP(up((void *)bt.nh0, s.nh.data(), sizeof(int32_t) * s.B));
-    CT_HIP(up(bt.ev_step, start.data(), sizeof(int64_t) * s.B));
-    CT_HIP(up(bt.ev_taken, zeros64.data(), sizeof(int64_t) * s.B));
-    CT_HIP(up(bt.call_steps, zeros64.data(), sizeof(int64_t) * s.B));
-    CT_HIP(up(bt.ref, ref.data(), sizeof(double) * 4 * s.B));
     CT_HIP(up((void *)bt.rngid, rngid.data(), sizeof(int32_t) * s.N));
-    CT_HIP(up(bt.pairs, zeros64.data(), sizeof(uint64_t) * s.B));
-    CT_HIP(up(bt.hsteps, zeros64.data(), sizeof(uint64_t) * s.B));
     CT_HIP(up((void *)bt.sigma, sigma.data(), sizeof(double) * s.B));
     CT_HIP(up((void *)bt.dep_off, dep_off.data(), sizeof(int32_t) * (s.B + 1)));
     CT_HIP(up((void *)bt.deposits, deps.data(), sizeof(double) * deps.size()));
     CT_HIP(up((void *)bt.x_off, x_off.data(), sizeof(int32_t) * (s.B + 1)));
     CT_HIP(up((void *)bt.xyz_in, xyz.data(), sizeof(double) * xyz.size()));
     CT_HIP(up((void *)bt.start, start.data(), sizeof(int64_t) * s.B));
-    CT_HIP(ct::launch_fill_i32(bt.pix, s.B * G1, 0, sm));
-    CT_HIP(ct::launch_seed(c->dp, bt, sm));
-    CT_HIP(ct::launch_compact(c->dp, bt, sm));
-    CT_HIP(ct::launch_summary(bt, c->dq.sc, sm));
-    CT_HIP(hipMemcpyAsync(c->h_sched, c->dq.sc, sizeof(ct::Sched), hipMemcpyDeviceToHost, sm));
-    CT_HIP(hipStreamSynchronize(sm));
-    c->n_active = s.B > 0 ? c->h_sched->active : 0;
-    c->steps = 0;
-    c->field_launches = 0;
-    c->field_ms = 0.0;
-    c->step_wall_ms = 0.0;
+    c->start_h = start;
+    st = reset_state(c);  // synchronises the stream (the host vectors may go)
+    if (st != CT_OK) return st;
     c->seeded = true;
     if (!noalloc && (c->p.options & CT_OPT_AUTOTUNE) && (c->p.physics_flags & CT_REPULSION) &&
         s.N > 0 && !spherical(c)) {

@@ -542,19 +542,36 @@ def test_full_work_queue_parks_and_resumes(ct, monkeypatch):
     np.testing.assert_array_equal(ref["pix"], r["pix"])
 
 
-def test_autotuned_launch_matches_oracle(ct):
-    """The autotuner only changes the launch shape: sampled events still meet
-    both tolerances, and the chosen configuration is reported."""
+def test_autotuned_launch_matches_oracle(ct, tmp_path, monkeypatch):
+    """The autotuner times candidate launches on the first steps of the
+    seeded batch and keeps the fastest.  It only changes the launch shape: the
+    run equals bit for bit a run with that launch set by hand, sampled events
+    meet both parity bars, FP32 keeps Newton pairs, and the choice is written
+    to the cache file, where a second context of the same shape finds it."""
+    cache = tmp_path / "launch_cache.txt"
+    monkeypatch.setenv("CT_TUNE_CACHE", str(cache))
+    monkeypatch.setenv("CT_TUNE_STEPS", "8")
     s, b = batch_8kev(n_events=64, seed=8)
     for prec in (FP64, FP32):
         with ct.Simulator(s, prec, options=ct.CT_OPT_AUTOTUNE) as sim:
             g = sim.run(b)
         st = g["stats"]
-        assert st.block_size in (128, 256) and st.targets_per_thread in (1, 2)
-        assert st.chunk_len in (256, 512, 768, 1280, 1536, 2304)
+        launch = (st.targets_per_thread, st.block_size, st.chunk_len)
+        if prec == FP32:
+            assert st.newton_pairs and launch[:2] == (1, 256) and launch[2] % 256 == 0, launch
+        same = gpu_run(ct, s, b, prec, launch=launch)
+        np.testing.assert_array_equal(g["xyz"], same["xyz"])
+        np.testing.assert_array_equal(g["cstep"], same["cstep"])
         for e in (0, 31, 63):
             o = oracle.run(s, b.event(e))
             if prec == FP64:
                 assert_fp64_parity(_event_slice(g, e), o, f"autotuned event {e}")
             else:
                 assert_fp32_parity(_event_slice(g, e), o, f"autotuned event {e}")
+        entries = [l for l in cache.read_text().splitlines() if f" p{prec} " in l]
+        assert len(entries) == 1 and entries[0].endswith(" ".join(map(str, launch))), entries
+        with ct.Simulator(s, prec, options=ct.CT_OPT_AUTOTUNE) as sim:  # reuses the entry
+            sim.seed(b)
+            st2 = sim.collect(carriers=False)["stats"]
+        assert (st2.targets_per_thread, st2.block_size, st2.chunk_len) == launch
+    assert len(cache.read_text().splitlines()) == 2
