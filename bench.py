@@ -165,6 +165,28 @@ def measured_traffic(model, units_per_launch, chunk_len=None):
                                      "1 GiB copy; " + os.path.basename(path))
 
 
+def counted_issue(kps):
+    """The step kernel's VALU lane-instructions per ordered pair and shader
+    clock from the committed counter summary of the 8 keV batch (whole
+    kernel: pair loop, staging, reaction sums, update, compaction), and the
+    issue fraction they give at this run's rate; None when the kernel's
+    sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_run_newton_batch_8kev_valu.md")
+    try:
+        vals = dict(line.split(":", 1) for line in open(path).read().splitlines()
+                    if line.startswith(("valu_lane_instr_per_pair:", "clock_ghz:",
+                                        "kernel_sources_sha256:")))
+    except OSError:
+        return None
+    if vals.get("kernel_sources_sha256", "").strip() != sources_digest("pairs"):
+        return None
+    per, clk = float(vals["valu_lane_instr_per_pair"]), float(vals["clock_ghz"]) * 1e9
+    return {"lane_instr_per_pair": per, "clock_ghz": clk / 1e9,
+            "frac": kps * per / VALU_ISSUE_PER_S,
+            "frac_at_counted_clock": kps * per / (256 * 64 * clk),
+            "source": os.path.basename(path)}
+
+
 def simulate(ct, sim, batch, max_steps=0):
     """Seed, step to completion (or max_steps), copy back pixel counts and run
     statistics."""
@@ -328,7 +350,8 @@ def roofline(t, traffic_units=None, traffic_model=None):
                             "note": "DPP moves and v_rsq_f32 partly co-issue with the FMAs, so "
                                     "the pair loop can run above this basis (frac above 1); the "
                                     "counters of the 8 keV batch read 66 lane-instructions per CU "
-                                    "per clock against 64"}}
+                                    "per clock against 64",
+                            "counted": counted_issue(kps) if newton and traffic_model == "pairs" else None}}
 
 
 def plain_rate(ct, torch, sensor, events, prec, max_steps=0):
