@@ -52,7 +52,7 @@ class OcEvent(C.Structure):
         ("energy_kev", C.c_double), ("n_carriers", C.c_int32), ("n_deposits", C.c_int32),
         ("sigma_um", C.c_double), ("deposits", C.POINTER(C.c_double)),
         ("xyz", C.POINTER(C.c_double)), ("ids", C.POINTER(C.c_int32)), ("start_step", C.c_int64),
-        ("n_electrons", C.c_int32),
+        ("n_electrons", C.c_int32), ("seg_len_um", C.c_double),
     ]
 
 
@@ -91,6 +91,8 @@ def lib():
                                        C.POINTER(C.c_int64), dp]
         L.oc_carrier_count.argtypes = [C.POINTER(OcParams), C.POINTER(OcEvent)]
         L.oc_carrier_count.restype = C.c_int32
+        L.oc_track_deposits.argtypes = [C.POINTER(OcParams), C.POINTER(OcEvent), C.c_uint64, dp]
+        L.oc_track_deposits.restype = None
         L.oc_initial_sigma.argtypes = [C.POINTER(OcEvent)]
         L.oc_initial_sigma.restype = C.c_double
         L.oc_pixel_bin.argtypes = [C.POINTER(OcParams), C.c_double, C.c_double]
@@ -241,8 +243,19 @@ def _events(batch):
         keep += [dep, xyz]
         evs[b] = OcEvent(float(batch.energy_kev[b]), int(batch.n_carriers[b]), nd,
                          float(batch.sigma_um[b]), _dp(dep), _dp(xyz), None,
-                         int(batch.start_step[b]), int(batch.n_electrons[b]))
+                         int(batch.start_step[b]), int(batch.n_electrons[b]),
+                         float(batch.seg_len_um[b]))
     return evs, keep
+
+
+def track_deposits(sensor, batch, b: int = 0) -> np.ndarray:
+    """The deposits of track event b ([n_deposits, 3]): the midpoints of the
+    walk the oracle draws from the event's start point."""
+    evs, keep = _events(batch)
+    out = np.zeros((int(batch.n_deposits[b]), 3))
+    lib().oc_track_deposits(C.byref(params(sensor)), C.byref(evs[b]),
+                            C.c_uint64(batch.first_event_id + b), _dp(out))
+    return out
 
 
 def hole_counts(sensor, batch) -> np.ndarray:

@@ -59,6 +59,15 @@
  *    (carrier id, step, event id, domain); domain 0 = hole diffusion at a
  *    step, domain 1 = initial cloud, domain 4 = electron diffusion at a step.  Uniforms (w + 0.5) 2^-32, Box-Muller
  *    normals: n0, n1 from (u0, u1), n2 from (u2, u3).
+ *  - Tracks (an event with seg_len_um > 0): the deposits are the midpoints
+ *    of a walk of n_deposits straight segments of length seg_len_um that
+ *    starts at the given point; the first segment points along -z (into
+ *    the sensor from the entrance side), each later segment k along an
+ *    isotropic unit vector from the Philox block of counter
+ *    (k, 0, event id, 3): cos(theta) = 1 - 2 u0, phi = 2 pi u1.  Walk points
+ *    and midpoints are folded back into [0, H] (mirror at either face).  The
+ *    paper has no track model; this is the reading of its deposit-based
+ *    seeding for an extended track.
  *  - Pixel integration: a grid_n x grid_n array of square pixels of side
  *    pitch centred on (0, 0); bin index floor((x + grid_n pitch / 2) / pitch)
  *    per axis; carriers outside the grid go to one overflow bin.
@@ -98,6 +107,7 @@ typedef struct {
     int64_t start_step;
     int32_t n_electrons;    /* with electrons: < 0 = one per hole; explicit events list the
                                electrons' positions (and ids) after the holes' */
+    double seg_len_um;      /* > 0: a track of n_deposits segments starting at deposits[0] */
 } oc_event;
 
 enum { OC_OK = 0, OC_EINVAL = -1, OC_EMAXSTEPS = -5, OC_ENONFINITE = -6 };
@@ -397,6 +407,43 @@ double oc_initial_sigma(const oc_event *ev)
     return 0.0044 * pow(ev->energy_kev, 1.75);
 }
 
+/* Mirror z at either face of the sensor until it lies in [0, H]. */
+static double fold_into_sensor(double z, double H)
+{
+    while (z < 0.0 || z > H) z = z < 0.0 ? -z : 2.0 * H - z;
+    return z;
+}
+
+/* The deposits of a track event: n_deposits segment midpoints of the walk
+ * described in the header ([n_deposits][3] out). */
+void oc_track_deposits(const oc_params *p, const oc_event *ev, uint64_t eid, double *out)
+{
+    const double H = p->thickness_um, L = ev->seg_len_um;
+    const uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
+    double px = ev->deposits[0], py = ev->deposits[1], pz = ev->deposits[2];
+    for (int32_t k = 0; k < ev->n_deposits; ++k) {
+        double dx = 0.0, dy = 0.0, dz = -1.0;
+        if (k > 0) {
+            const uint32_t ctr[4] = {(uint32_t)k, 0u, (uint32_t)eid, 3u};
+            uint32_t w[4];
+            oc_philox4x32_10(ctr, key, w);
+            const double cos_t = 1.0 - 2.0 * to_unit(w[0]);
+            const double sin_t = sqrt(1.0 - cos_t * cos_t);
+            const double phi = 2.0 * PI * to_unit(w[1]);
+            dx = sin_t * cos(phi);
+            dy = sin_t * sin(phi);
+            dz = cos_t;
+        }
+        const double qx = px + L * dx, qy = py + L * dy, qz = pz + L * dz;
+        out[3 * k + 0] = 0.5 * (px + qx);
+        out[3 * k + 1] = 0.5 * (py + qy);
+        out[3 * k + 2] = fold_into_sensor(0.5 * (pz + qz), H);
+        px = qx;
+        py = qy;
+        pz = fold_into_sensor(qz, H);
+    }
+}
+
 int32_t oc_pixel_bin(const oc_params *p, double x, double y)
 {
     const int32_t G = p->grid_n;
@@ -479,6 +526,14 @@ static int run_event(const oc_params *p, const oc_event *ev, uint64_t eid, int p
     *hole_steps_out = 0;
     if (n <= 0) return OC_OK;
     if (ev->n_deposits > 0 && ne > 0 && ne != nh) return OC_EINVAL;
+    /* a track's deposits come from its walk */
+    double *track = NULL;
+    const double *deposits = ev->deposits;
+    if (ev->seg_len_um > 0.0) {
+        track = malloc(3 * sizeof(double) * (size_t)ev->n_deposits);
+        oc_track_deposits(p, ev, eid, track);
+        deposits = track;
+    }
 
     oc_work w;
     const size_t nd = (size_t)n;
@@ -510,7 +565,7 @@ static int run_event(const oc_params *p, const oc_event *ev, uint64_t eid, int p
         cstep[i] = -1;
         if (ev->n_deposits > 0) {
             if (i < w.nh) {
-                const double *d = ev->deposits + 3 * (i % ev->n_deposits);
+                const double *d = deposits + 3 * (i % ev->n_deposits);
                 double g[3];
                 oc_normals3(p->seed, (uint32_t)w.id[i], 0u, (uint32_t)eid, 1u, g);
                 w.x[i] = d[0] + sigma * g[0];
@@ -608,6 +663,7 @@ done:
     free(w.ax); free(w.ay); free(w.az); free(w.aq);
     free(w.sx); free(w.sy); free(w.sz);
     free(w.id); free(w.alive); free(w.act);
+    free(track);
     return status;
 }
 
@@ -628,7 +684,8 @@ int oc_run(const oc_params *p, const oc_event *ev, int32_t n_events, uint64_t fi
     off[0] = 0;
     for (int32_t b = 0; b < n_events; ++b) {
         if (ev[b].n_deposits < 0 || (ev[b].n_deposits == 0 && ev[b].n_carriers > 0 && !ev[b].xyz) ||
-            (ev[b].n_deposits > 0 && !ev[b].deposits)) {
+            (ev[b].n_deposits > 0 && !ev[b].deposits) || !(ev[b].seg_len_um >= 0.0) ||
+            !isfinite(ev[b].seg_len_um) || (ev[b].seg_len_um > 0.0 && ev[b].n_deposits == 0)) {
             free(off);
             return OC_EINVAL;
         }

@@ -15,6 +15,7 @@ from .events import (  # noqa: F401
     mixed_energy,
     gamma_60kev,
     track_200kev,
+    track_walks,
     explicit_batch,
     GenParams,
     generator_25kev,

@@ -75,7 +75,11 @@ class Batch:
                     the energy-dependent initial width of the paper (Eq. 2)
     n_deposits[b]   >= 1: Gaussian cloud(s) around the deposit points;
                     0: explicit carrier positions taken from ``xyz``
-    deposits        [sum n_deposits, 3] deposit centres, in event order
+    seg_len_um[b]   > 0: a track whose n_deposits deposits the simulator
+                    places itself, at the midpoints of a walk of segments of
+                    this length from one start point; 0: deposits given
+    deposits        deposit centres in event order: n_deposits rows per
+                    event, one row (the track's start) per track event
     xyz             [sum of explicit positions, 3], in event order
     start_step[b]   step index of the given state (0 for a fresh event)
     first_event_id  event b uses id first_event_id + b in the RNG counter
@@ -91,6 +95,7 @@ class Batch:
     first_event_id: int = 0
     name: str = ""
     n_electrons: Optional[np.ndarray] = None
+    seg_len_um: Optional[np.ndarray] = None
 
     def __post_init__(self):
         self.energy_kev = np.ascontiguousarray(self.energy_kev, dtype=np.float64)
@@ -107,8 +112,11 @@ class Batch:
         if self.n_electrons is None:
             self.n_electrons = np.where(self.n_deposits > 0, -1, 0)
         self.n_electrons = np.ascontiguousarray(self.n_electrons, dtype=np.int32).reshape(B)
-        if int(self.n_deposits.sum()) != self.deposits.shape[0]:
-            raise ValueError("deposits rows must equal sum(n_deposits)")
+        if self.seg_len_um is None:
+            self.seg_len_um = np.zeros(B)
+        self.seg_len_um = np.ascontiguousarray(self.seg_len_um, dtype=np.float64).reshape(B)
+        if int(self.deposit_rows().sum()) != self.deposits.shape[0]:
+            raise ValueError("deposits rows must equal the events' deposit rows")
 
     @property
     def n_events(self) -> int:
@@ -119,9 +127,13 @@ class Batch:
         return np.where(self.n_deposits == 0,
                         self.n_carriers.astype(np.int64) + np.maximum(self.n_electrons, 0), 0)
 
+    def deposit_rows(self) -> np.ndarray:
+        """Rows of ``deposits`` that each event owns (a track: its start)."""
+        return np.where(self.seg_len_um > 0, 1, self.n_deposits).astype(np.int64)
+
     def dep_offsets(self) -> np.ndarray:
         off = np.zeros(self.n_events + 1, dtype=np.int64)
-        np.cumsum(self.n_deposits, out=off[1:])
+        np.cumsum(self.deposit_rows(), out=off[1:])
         return off
 
     def event(self, b: int) -> "Batch":
@@ -148,7 +160,7 @@ class Batch:
                 deposits=self.deposits[doff[b]:doff[b + 1]], xyz=xyz,
                 start_step=self.start_step[b:b + 1],
                 first_event_id=self.first_event_id + b, name=f"{self.name}[{b}]",
-                n_electrons=self.n_electrons[b:b + 1]))
+                n_electrons=self.n_electrons[b:b + 1], seg_len_um=self.seg_len_um[b:b + 1]))
         return out
 
     def head(self, n: int) -> "Batch":
@@ -162,7 +174,7 @@ class Batch:
         return Batch(self.energy_kev[:n], self.n_carriers[:n], self.sigma_um[:n],
                      self.n_deposits[:n], self.deposits[:doff[n]], xyz,
                      self.start_step[:n], self.first_event_id, f"{self.name}[:{n}]",
-                     self.n_electrons[:n])
+                     self.n_electrons[:n], self.seg_len_um[:n])
 
 
 # ---------------------------------------------------------------- samplers
@@ -280,6 +292,25 @@ def track_200kev(n_events: int = 16, seed: int = 0, n_segments: int = 40,
     b = Batch(energy_kev=np.full(n_events, 200.0), n_carriers=np.full(n_events, _N_AT[200.0]),
               sigma_um=np.full(n_events, 0.5), n_deposits=np.full(n_events, n_segments),
               deposits=np.array(deps), name="track_200kev")
+    return s, b
+
+
+def track_walks(n_events: int = 16, seed: int = 0, n_segments: int = 40, seg_len_um: float = 5.0,
+                energy_kev: float = 200.0, n_carriers: Optional[int] = None,
+                sigma_um: float = 0.5) -> tuple[Sensor, Batch]:
+    """Tracks described by their start point only: the simulator draws each
+    walk itself (segment directions from its counter-based generator).  The
+    sensor is that of track_200kev; each walk starts on the entrance side
+    (z = H) at a point uniform over the central pixel."""
+    s = Sensor(thickness_um=320.0, v_bias=150.0, v_dep=60.0, dt_ns=0.05, seed=seed)
+    rng = _rng(seed, 6)
+    H = s.thickness_um
+    start = np.column_stack([rng.uniform(-0.5 * s.pitch_um, 0.5 * s.pitch_um, (n_events, 2)),
+                             np.full(n_events, H)])
+    n = _N_AT.get(energy_kev, 0) if n_carriers is None else n_carriers
+    b = Batch(energy_kev=np.full(n_events, energy_kev), n_carriers=np.full(n_events, n),
+              sigma_um=np.full(n_events, sigma_um), n_deposits=np.full(n_events, n_segments),
+              deposits=start, name="track_walks", seg_len_um=np.full(n_events, seg_len_um))
     return s, b
 
 
