@@ -162,7 +162,18 @@ typedef struct {
  * z <= 0 are collected at step start_step; electrons below the pixel plane
  * are mirrored to -z and electrons at z >= H are collected at start_step.
  * Diffusion draws use counter (id, step, event id, 0) for holes and
- * (id, step, event id, 4) for electrons. */
+ * (id, step, event id, 4) for electrons.
+ *
+ * Tracks (seg_len_um > 0; the paper has no track model, this extends the
+ * deposit-based seeding of Algorithm 1 to an extended track): deposits holds
+ * one point, the track's start, and the library places the event's
+ * n_deposits deposits itself, on the device, at the midpoints of a walk of
+ * n_deposits straight segments of length seg_len_um from that start.
+ * Segment 0 points along -z; segment k >= 1 along the isotropic unit vector
+ * of the Philox block at counter (k, 0, event id, 3), with
+ * cos(theta) = 1 - 2 u0 and phi = 2 pi u1 (u = (w + 0.5) 2^-32).  Walk points
+ * and midpoints are folded back into [0, H] (mirrored at either face).  The
+ * carriers then sit on the deposits as for any multi-deposit event. */
 typedef struct {
     double energy_kev;         /* used when n_carriers <= 0 or sigma_um < 0 */
     int32_t n_carriers;        /* > 0, or <= 0 for round(1000 E / pair_energy_ev) (Algorithm 1) */
@@ -176,6 +187,9 @@ typedef struct {
     int32_t n_electrons;       /* with CT_ELECTRONS: < 0 one per hole (cloud events; explicit
                                   events then list n_carriers electrons), >= 0 that many; without
                                   CT_ELECTRONS it must be <= 0 */
+    double seg_len_um;         /* > 0: a track of n_deposits (>= 1) segments of this length
+                                  whose start is deposits[0..2]; 0: deposits as given.
+                                  Negative or not finite: CT_EINVAL */
 } ct_event_desc;
 
 typedef struct {

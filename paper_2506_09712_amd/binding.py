@@ -65,7 +65,7 @@ class ct_event_desc(C.Structure):
         ("energy_kev", C.c_double), ("n_carriers", C.c_int32), ("n_deposits", C.c_int32),
         ("sigma_um", C.c_double), ("deposits", C.POINTER(C.c_double)),
         ("xyz", C.POINTER(C.c_double)), ("ids", C.POINTER(C.c_int32)), ("start_step", C.c_int64),
-        ("n_electrons", C.c_int32),
+        ("n_electrons", C.c_int32), ("seg_len_um", C.c_double),
     ]
 
 
@@ -189,7 +189,8 @@ class EventDescs:
             self._keep += [dep, xyz]
             self.arr[b] = ct_event_desc(float(batch.energy_kev[b]), int(batch.n_carriers[b]), nd,
                                         float(batch.sigma_um[b]), _dp(dep), _dp(xyz), idp,
-                                        int(batch.start_step[b]), int(batch.n_electrons[b]))
+                                        int(batch.start_step[b]), int(batch.n_electrons[b]),
+                                        float(batch.seg_len_um[b]))
 
 
 # ------------------------------------------------------------ wrappers

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libct.so")
-SOURCES = ["ct_kernels.hip", "ct_sph.hip", "ct_gen.hip", "ct_capi.cpp"]
+SOURCES = ["ct_kernels.hip", "ct_sph.hip", "ct_gen.hip", "ct_track.hip", "ct_capi.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -22,6 +22,7 @@
 #include "ct.h"
 #include "ct_internal.hpp"
 #include "ct_sph_layout.hpp"
+#include "ct_track.hpp"
 
 namespace {
 
@@ -164,7 +165,7 @@ double initial_sigma(const ct_event_desc &e)
 struct Layout {
     size_t off, n_act, n_hole, nh0, ev_step, ev_taken, call_steps, ref, pos, idx, nidx, rngid,
         out_xyz, out_cstep, pix, pairs, hsteps, sigma, dep_off, deposits, x_off, xyz_in, start,
-        sph, total;
+        seg_len, sph, total;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -202,6 +203,7 @@ Layout make_layout(int64_t B, int64_t N, int64_t n_dep, int64_t n_exp, int G1, b
     L.x_off = take(sizeof(int32_t) * (B + 1));
     L.xyz_in = take(sizeof(double) * 3 * n_exp);
     L.start = take(sizeof(int64_t) * B);
+    L.seg_len = take(sizeof(double) * B);
     L.sph = take(spherical ? sizeof(double) * 2 * N : 0);
     L.total = o;
     return L;
@@ -209,6 +211,7 @@ Layout make_layout(int64_t B, int64_t N, int64_t n_dep, int64_t n_exp, int G1, b
 
 struct BatchShape {
     int64_t B = 0, N = 0, n_dep = 0, n_exp = 0;
+    bool tracks = false;  // some event is a track (its deposits are computed at seeding)
     int32_t n_max = 0;
     std::vector<int32_t> n;   // carriers of each event (holes + electrons)
     std::vector<int32_t> nh;  // holes of each event
@@ -227,6 +230,10 @@ ct_status shape_of(const ct_sensor_params &p, const ct_event_desc *ev, int32_t B
         const ct_event_desc &e = ev[b];
         if (e.n_deposits < 0) return fail(CT_EINVAL, "event %d: n_deposits < 0", b);
         if (e.n_deposits > 0 && !e.deposits) return fail(CT_EINVAL, "event %d: deposits missing", b);
+        if (!(e.seg_len_um >= 0.0) || !std::isfinite(e.seg_len_um))
+            return fail(CT_EINVAL, "event %d: seg_len_um must be finite and >= 0", b);
+        if (e.seg_len_um > 0.0 && e.n_deposits == 0)
+            return fail(CT_EINVAL, "event %d: a track has n_deposits >= 1 segments", b);
         if ((e.n_carriers <= 0 || e.sigma_um < 0.0) && !(e.energy_kev > 0.0) && e.n_deposits > 0)
             return fail(CT_EINVAL, "event %d: energy needed for the carrier count or width", b);
         if (e.n_deposits == 0 && e.n_carriers <= 0 && e.energy_kev != 0.0)
@@ -250,6 +257,7 @@ ct_status shape_of(const ct_sensor_params &p, const ct_event_desc *ev, int32_t B
         s.n_max = std::max(s.n_max, n);
         s.n_dep += e.n_deposits;
         if (e.n_deposits == 0) s.n_exp += n;
+        if (e.seg_len_um > 0.0) s.tracks = true;
     }
     if (s.N > INT32_MAX / 2) return fail(CT_EINVAL, "batch has too many carriers (%lld)", (long long)s.N);
     return CT_OK;
@@ -1075,7 +1083,7 @@ ct_status seed(ct_ctx *c, const ct_event_desc *ev, int32_t n_events, uint64_t fi
     // host-side staging of the event descriptions
     const int G1 = c->p.grid_n * c->p.grid_n + 1;
     std::vector<int32_t> off(s.B + 1), dep_off(s.B + 1), x_off(s.B + 1), rngid(s.N);
-    std::vector<double> sigma(s.B), deps(3 * s.n_dep), xyz(3 * s.n_exp);
+    std::vector<double> sigma(s.B), deps(3 * s.n_dep), xyz(3 * s.n_exp), seg_len(s.B);
     std::vector<int64_t> start(s.B);
     off[0] = dep_off[0] = x_off[0] = 0;
     for (int32_t b = 0; b < s.B; ++b) {
@@ -1086,7 +1094,10 @@ ct_status seed(ct_ctx *c, const ct_event_desc *ev, int32_t n_events, uint64_t fi
         x_off[b + 1] = x_off[b] + (e.n_deposits == 0 ? n : 0);
         sigma[b] = e.n_deposits > 0 ? initial_sigma(e) : 0.0;
         start[b] = e.start_step;
-        for (int32_t d = 0; d < 3 * e.n_deposits; ++d) {
+        seg_len[b] = e.seg_len_um;
+        // a track lists its start only; the device fills its deposit slots
+        const int32_t given = e.seg_len_um > 0.0 ? 3 : 3 * e.n_deposits;
+        for (int32_t d = 0; d < given; ++d) {
             if (!std::isfinite(e.deposits[d]))
                 return fail(CT_ENONFINITE, "event %d: deposit not finite", b);
             deps[3 * (size_t)dep_off[b] + d] = e.deposits[d];
@@ -1164,6 +1175,12 @@ ct_status seed(ct_ctx *c, const ct_event_desc *ev, int32_t n_events, uint64_t fi
     CT_HIP(up((void *)bt.x_off, x_off.data(), sizeof(int32_t) * (s.B + 1)));
     CT_HIP(up((void *)bt.xyz_in, xyz.data(), sizeof(double) * xyz.size()));
     CT_HIP(up((void *)bt.start, start.data(), sizeof(int64_t) * s.B));
+    if (s.tracks) {
+        double *seg = at<double>(w, L.seg_len);
+        CT_HIP(up(seg, seg_len.data(), sizeof(double) * s.B));
+        CT_HIP(ct::launch_track(c->dp, (int32_t)s.B, first_event_id, bt.dep_off, seg,
+                                const_cast<double *>(bt.deposits), sm));
+    }
     c->start_h = start;
     st = reset_state(c);  // synchronises the stream (the host vectors may go)
     if (st != CT_OK) return st;

@@ -129,3 +129,28 @@ def test_invalid_events_rejected(ct):
     with pytest.raises(ct.CtError) as e:
         ct.ct_event_carriers(p, d)
     assert e.value.status == -1
+
+
+def test_track_events_validated_on_the_host(ct):
+    """A track (seg_len_um > 0) lists one start point and n_deposits >= 1
+    segments; a negative or non-finite length is rejected, as is a track
+    with no segment."""
+    from workloads import Batch, Sensor, track_walks
+    s, b = track_walks(n_events=3, n_segments=40)
+    p = ct.make_params(s)
+    assert list(ct.ct_event_carriers(p, ct.EventDescs(b))) == [55556] * 3
+    # the workspace holds the 40 deposits of each track, not just its start
+    flat = Batch(b.energy_kev, b.n_carriers, b.sigma_um, b.n_deposits, np.zeros((120, 3)))
+    assert ct.ct_workspace_bytes(p, ct.EventDescs(b)) >= ct.ct_workspace_bytes(p, ct.EventDescs(flat))
+    for bad in (-1.0, float("inf"), float("nan")):
+        d = ct.EventDescs(b)
+        d.arr[1].seg_len_um = bad
+        with pytest.raises(ct.CtError) as e:
+            ct.ct_event_carriers(p, d)
+        assert e.value.status == -1 and "seg_len_um" in str(e.value), bad
+    d = ct.EventDescs(Batch([10.0], [5], [0.0], [1], [[0, 0, 10.0]]))
+    d.arr[0].n_deposits = 0
+    d.arr[0].seg_len_um = 5.0
+    with pytest.raises(ct.CtError) as e:
+        ct.ct_event_carriers(p, d)
+    assert e.value.status == -1
