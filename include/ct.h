@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CT_ABI_VERSION 2u
+#define CT_ABI_VERSION 3u
 
 typedef struct ct_ctx ct_ctx; /* opaque, owned by the library */
 
@@ -67,9 +67,11 @@ typedef enum {
 
 /* Arithmetic of the pairwise field.  Positions and the time integration are
  * FP64 in both modes.  CT_FP32: the pair terms are summed in FP32 on
- * coordinates relative to the event centroid over each LDS tile of sources,
- * and the tile sums are added in FP64; CT_FP64: everything in FP64 on
- * absolute coordinates.  An event's sources are split into chunks whose
+ * coordinates relative to the FP64 position of the first carrier of the
+ * target's tile (256 consecutive slots; multi-deposit events occupy their
+ * slots deposit by deposit, so a tile is spatially compact) over each LDS
+ * tile of sources, and the tile sums are added in FP64; CT_FP64: everything
+ * in FP64 on absolute coordinates.  An event's sources are split into chunks whose
  * length depends only on the event's own hole count and the launch
  * configuration (ct_set_launch), and the chunk sums are added in chunk
  * order, so an event's result does not depend on the rest of the batch. */

@@ -27,7 +27,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 # kernels compiled with different tuning macros)
 LIB_PATH = os.environ.get("CT_LIBRARY") or os.path.join(_PKG, "libct.so")
 
-CT_ABI_VERSION = 2
+CT_ABI_VERSION = 3
 CT_OK, CT_EINVAL, CT_ESTATE, CT_ENOMEM, CT_EDEVICE, CT_EMAXSTEPS, CT_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 CT_FP64, CT_FP32 = 0, 1
 CT_MOB_JACOBONI, CT_MOB_CONSTANT = 0, 1

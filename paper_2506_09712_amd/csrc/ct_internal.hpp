@@ -263,7 +263,7 @@ __host__ __device__ inline void event_chunks(int n, int bs, int chunk, int &len,
 // deposits (carrier k sits on deposit k mod nd): slots run deposit by
 // deposit, each deposit's carriers in increasing order, so that every tile
 // of consecutive slots is spatially compact (FP32 coordinates are formed
-// relative to a tile's own centroid).  A bijection of [0, n).
+// relative to a tile's first carrier).  A bijection of [0, n).
 __host__ __device__ inline int deposit_major(int s, int n, int nd)
 {
     if (nd <= 1) return s;
