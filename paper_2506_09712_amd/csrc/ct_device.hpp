@@ -116,13 +116,13 @@ __device__ __forceinline__ uint32_t add_relaxed(uint32_t *p, uint32_t v)
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Decrement of a completion counter (thread 0, after a workgroup barrier):
-// releases the workgroup's results; the caller that takes the counter to
-// zero also acquires everyone else's.
-__device__ __forceinline__ bool dec_is_last(int32_t *p)
+// Decrement of a completion counter by `by` (thread 0, after a workgroup
+// barrier): releases the workgroup's results; the caller that takes the
+// counter to zero also acquires everyone else's.
+__device__ __forceinline__ bool dec_is_last(int32_t *p, int32_t by = 1)
 {
-    const int32_t left = __hip_atomic_fetch_add(p, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (left != 1) return false;
+    const int32_t left = __hip_atomic_fetch_add(p, -by, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (left != by) return false;
     fence_acquire();
     return true;
 }

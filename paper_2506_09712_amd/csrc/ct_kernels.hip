@@ -758,9 +758,18 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
             s_fin[0] = a;
         }
         __syncthreads();
+        // The tiles this item completed (often several: its own and partners
+        // whose last reaction it delivered) are updated in one pass, without a
+        // barrier between them, and counted off the event with one atomic, so
+        // that the end of an event's step waits for one store round trip and
+        // one release instead of one of each per tile.  (Loading a hole's
+        // state or several partial slots ahead of the sums was slower: the
+        // extra registers spill at this occupancy.)
+        int done_tiles = 0;
         for (int k = 0; k < ntouch; ++k) {
             const int u = s_fin[k];
             if (u < 0) continue;
+            ++done_tiles;
             const int s = u * BS + tid;
             if (s < n) {
                 double fx = ex, fy = ey, fz = ez;
@@ -778,16 +787,18 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
                 field_or_advance(dp, bt, b, base + s, dp.K * fx, dp.K * fy, dp.K * fz,
                                  ra.field_only, ra.field_out);
             }
+        }
+        if (done_tiles > 0) {
             wait_own_stores();
             __syncthreads();
-            if (tid == 0) s_go = dec_is_last(&dq.tiles_left[b * kEventLine]);
+            if (tid == 0) s_go = dec_is_last(&dq.tiles_left[b * kEventLine], done_tiles);
             __syncthreads();
-            if (!s_go) continue;
-
+        }
+        if (done_tiles > 0 && s_go) {
             // every tile of the event's step is updated
             if (ra.field_only) {
                 if (tid == 0) add_relaxed(&sc->done.v, 1u);
-                break;
+                continue;
             }
             int holes_kept = 0;
             const int kept = compact_event<BS>(bt, b, n, nh, dp.H, 1, s_wcount, s_wsum, holes_kept);
@@ -831,7 +842,6 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
                 __syncthreads();  // the write-back has completed before any sequence word is set
                 for (int i = tid; i < items; i += BS) st_relaxed(&dq.seq[t0q + i], dq.gen);
             }
-            break;  // only one tile is the event's last
         }
     }
 }
