@@ -318,8 +318,8 @@ def timed_runs(ct, torch, sensor, batch, steps, warmup, options, launch, label):
 def roofline(t, traffic_units=None, traffic_model=None):
     """The step kernel against the published FP32 peak (20 flop per ordered
     pair, the N-body convention: a pair-equivalent rate) and against the VALU
-    issue bound of its compiled pair loop (one vector instruction per lane per
-    clock)."""
+    issue rate its compiled pair loop would need (one vector instruction per
+    lane per clock), with what limits it."""
     kps = t["kernel_pairs_per_s"]
     newton = t["newton_pairs"]
     per_pair = NEWTON_INSTR_PER_PAIR if newton else ONE_SIDED_INSTR_PER_PAIR
@@ -348,10 +348,15 @@ def roofline(t, traffic_units=None, traffic_model=None):
                             "pairs_per_s": VALU_ISSUE_PER_S / per_pair,
                             "frac": kps * per_pair / VALU_ISSUE_PER_S,
                             "note": "DPP moves and v_rsq_f32 partly co-issue with the FMAs, so "
-                                    "the pair loop can run above this basis (frac above 1); the "
-                                    "counters of the 8 keV batch read 66 lane-instructions per CU "
-                                    "per clock against 64",
-                            "counted": counted_issue(kps) if newton and traffic_model == "pairs" else None}}
+                                    "a pair loop can issue above this basis (a standalone "
+                                    "probe of the sweep: 66-69 lane-instructions per CU per clock "
+                                    "against 64)",
+                            "counted": counted_issue(kps) if newton and traffic_model == "pairs" else None},
+            "limiter": "the per-step chain of each event (its step's items, then the tile "
+                       "updates and the compaction that publish the next step), not the VALU "
+                       "issue rate: on the 8 keV batch a copy of the kernel with half the "
+                       "pair-loop instructions ran no faster, and workgroups wait for work "
+                       "about a fifth of the time"}
 
 
 def plain_rate(ct, torch, sensor, events, prec, max_steps=0):
