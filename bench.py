@@ -154,13 +154,17 @@ def measured_traffic(model, units_per_launch, chunk_len=None):
         return None, "no counter summary"
     unit = "bytes_per_event" if model == "generator" else "bytes_per_hole_step"
     vals = dict(line.split(":", 1) for line in text.splitlines()
-                if line.startswith((unit + ":", "kernel_sources_sha256:", "chunk_len:")))
+                if line.startswith((unit, "kernel_sources_sha256:", "chunk_len:")))
     if vals.get("kernel_sources_sha256", "").strip() != sources_digest(model):
         return None, "kernel changed since the counters were taken"
-    if chunk_len is not None and int(vals.get("chunk_len", -1)) != chunk_len:
-        return None, (f"counters taken with source chunks of {vals.get('chunk_len', '?').strip()}, "
-                      f"this launch uses {chunk_len}")
-    per = float(vals[unit])
+    per = vals.get(unit)
+    if chunk_len is not None:
+        per = vals.get(f"{unit}_chunk{chunk_len}")
+        if per is None and int(vals.get("chunk_len", -1)) == chunk_len:
+            per = vals.get(unit)
+        if per is None:
+            return None, f"no counters taken with source chunks of {chunk_len}"
+    per = float(per)
     return per * units_per_launch, ("FETCH_SIZE and WRITE_SIZE per unit of work, scaled by a "
                                      "1 GiB copy; " + os.path.basename(path))
 

@@ -782,6 +782,8 @@ void store_tune_cache(const std::string &key, const ct::LaunchCfg &cfg)  // g_tu
 // Steps of the whole-run prefix each candidate is timed on: CT_TUNE_STEPS,
 // else enough for about 2e10 pair evaluations (the first step's pairs set
 // the pace), between 2 and 32.
+constexpr float kTuneMargin = 0.01f;
+
 int64_t tune_steps(const BatchShape &s)
 {
     const char *v = std::getenv("CT_TUNE_STEPS");
@@ -789,15 +791,20 @@ int64_t tune_steps(const BatchShape &s)
     if (k >= 1) return (int64_t)k;
     double pairs = 0.0;
     for (int32_t n : s.n) pairs += (double)n * (double)n;
-    const double steps = pairs > 0.0 ? 2e10 / pairs : 32.0;
-    return (int64_t)std::max(2.0, std::min(32.0, std::floor(steps)));
+    // about 4e11 pair evaluations (a second or less on this GPU): most of a
+    // run for batches of small events, which rank best on whole runs, and
+    // 8-30 steps of the large ones
+    const double steps = pairs > 0.0 ? 4e11 / pairs : 400.0;
+    return (int64_t)std::max(2.0, std::min(400.0, std::floor(steps)));
 }
 
 // Time the first tune_steps() steps of the seeded batch under each candidate
 // launch (the persistent kernel only, HIP events; the better of two runs,
-// each from the freshly seeded state) and keep the fastest.  Every candidate
-// runs the same steps of the same events, so the fastest prefix is the one
-// with the highest pair rate.  Candidates keep Newton pairs where the context
+// each from the freshly seeded state) and keep the fastest, unless it beats
+// the context's current launch by less than kTuneMargin: a prefix ranks
+// launches whose whole runs differ by a percent or two no better than that,
+// so near-ties keep the default.  Every candidate runs the same steps of the
+// same events, so the fastest prefix is the one with the highest pair rate.  Candidates keep Newton pairs where the context
 // uses them (FP32, repulsion, CT_OPT_ONE_SIDED unset): one target per thread,
 // blocks of 256, chunks of 1 to 15 tiles.  The state is the seeded one
 // afterwards.
@@ -831,7 +838,8 @@ ct_status autotune(ct_ctx *c)
                     {2, 256, 1280}, {1, 128, 256}, {1, 128, 512}};
         }
         const int64_t K = tune_steps(c->shape);
-        float best_ms = 1e30f;
+        float best_ms = 1e30f, current_ms = 1e30f;
+        const ct::LaunchCfg current = best;
         for (const ct::LaunchCfg &cfg : cand) {
             st = prepare_queue(c, cfg);
             if (st != CT_OK) return st;
@@ -849,11 +857,14 @@ ct_status autotune(ct_ctx *c)
                 }
                 ms_min = std::min(ms_min, (float)(c->field_ms - before));
             }
+            if (cfg.kt == current.kt && cfg.bs == current.bs && cfg.chunk == current.chunk)
+                current_ms = ms_min;
             if (ms_min < best_ms) {
                 best_ms = ms_min;
                 best = cfg;
             }
         }
+        if (best_ms > (1.0f - kTuneMargin) * current_ms) best = current;
         std::lock_guard<std::mutex> lk(g_tuned_mu);
         store_tune_cache(key, best);
     }
