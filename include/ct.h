@@ -108,9 +108,10 @@ enum {
     CT_OPT_TIMING = 1u,   /* time every run of the step kernel with HIP events (ct_run_stats) */
     CT_OPT_AUTOTUNE = 4u, /* on seeding, time candidate launch configurations on the first
                              steps of the seeded batch (environment variable CT_TUNE_STEPS, by
-                             default as many as make about 4e11 pair evaluations, 2 to 400; each
+                             default as many as make about 6e11 pair evaluations, 2 to 1000; each
                              from the freshly seeded state, the persistent kernel alone) and
-                             keep the fastest if it beats the current launch by 1% or more;
+                             keep the fastest (when those steps do not finish the batch, only if
+                             it beats the current launch by 1% or more);
                              candidates keep Newton pairs
                              where the context uses them.  The choice is cached per device
                              architecture, compute units, precision, physics switches,

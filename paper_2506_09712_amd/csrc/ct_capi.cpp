@@ -779,10 +779,13 @@ void store_tune_cache(const std::string &key, const ct::LaunchCfg &cfg)  // g_tu
     }
 }
 
-// Steps of the whole-run prefix each candidate is timed on: CT_TUNE_STEPS,
-// else enough for about 2e10 pair evaluations (the first step's pairs set
-// the pace), between 2 and 32.
+// Least relative gain over the current launch that a candidate timed on a
+// prefix (not on whole runs) must show to replace it.
 constexpr float kTuneMargin = 0.01f;
+
+// Steps of the whole-run prefix each candidate is timed on: CT_TUNE_STEPS,
+// else enough for about 6e11 pair evaluations at the first step's pair
+// count, between 2 and 1000.
 
 int64_t tune_steps(const BatchShape &s)
 {
@@ -791,23 +794,24 @@ int64_t tune_steps(const BatchShape &s)
     if (k >= 1) return (int64_t)k;
     double pairs = 0.0;
     for (int32_t n : s.n) pairs += (double)n * (double)n;
-    // about 4e11 pair evaluations (a second or less on this GPU): most of a
-    // run for batches of small events, which rank best on whole runs, and
-    // 8-30 steps of the large ones
-    const double steps = pairs > 0.0 ? 4e11 / pairs : 400.0;
-    return (int64_t)std::max(2.0, std::min(400.0, std::floor(steps)));
+    // about 6e11 pair evaluations (a second or two on this GPU): whole runs
+    // of batches of small events, 10-40 steps of the large ones
+    const double steps = pairs > 0.0 ? 6e11 / pairs : 1000.0;
+    return (int64_t)std::max(2.0, std::min(1000.0, std::floor(steps)));
 }
 
 // Time the first tune_steps() steps of the seeded batch under each candidate
-// launch (the persistent kernel only, HIP events; the better of two runs,
-// each from the freshly seeded state) and keep the fastest, unless it beats
-// the context's current launch by less than kTuneMargin: a prefix ranks
-// launches whose whole runs differ by a percent or two no better than that,
-// so near-ties keep the default.  Every candidate runs the same steps of the
-// same events, so the fastest prefix is the one with the highest pair rate.  Candidates keep Newton pairs where the context
-// uses them (FP32, repulsion, CT_OPT_ONE_SIDED unset): one target per thread,
-// blocks of 256, chunks of 1 to 15 tiles.  The state is the seeded one
-// afterwards.
+// launch (the persistent kernel only, HIP events; the best of three runs,
+// each from the freshly seeded state) and keep the fastest.  Every candidate
+// runs the same steps of the same events, so the fastest prefix is the one
+// with the highest pair rate.  When the steps timed did not finish the
+// batch, the fastest must beat the context's current launch by kTuneMargin:
+// a prefix does not rank launches whose whole runs differ by less than that
+// (a 60 keV batch's first steps favour shorter chunks that lose over the
+// whole run), so near-ties keep the default.  Candidates keep Newton pairs
+// where the context uses them (FP32, repulsion, CT_OPT_ONE_SIDED unset): one
+// target per thread, blocks of 256, chunks of 1 to 15 tiles.  The state is
+// the seeded one afterwards.
 ct_status autotune(ct_ctx *c)
 {
     const bool newton = resolve_cfg(c, ct::LaunchCfg{1, ct::kSymTile, ct::kSymTile}).newton != 0;
@@ -840,11 +844,12 @@ ct_status autotune(ct_ctx *c)
         const int64_t K = tune_steps(c->shape);
         float best_ms = 1e30f, current_ms = 1e30f;
         const ct::LaunchCfg current = best;
+        bool whole_runs = true;  // every timed prefix finished the batch
         for (const ct::LaunchCfg &cfg : cand) {
             st = prepare_queue(c, cfg);
             if (st != CT_OK) return st;
             float ms_min = 1e30f;
-            for (int rep = 0; rep < 2; ++rep) {
+            for (int rep = 0; rep < 3; ++rep) {
                 st = reset_state(c);
                 if (st != CT_OK) return st;
                 if (c->n_active == 0) break;
@@ -857,6 +862,7 @@ ct_status autotune(ct_ctx *c)
                 }
                 ms_min = std::min(ms_min, (float)(c->field_ms - before));
             }
+            if (c->h_sched->active != 0) whole_runs = false;
             if (cfg.kt == current.kt && cfg.bs == current.bs && cfg.chunk == current.chunk)
                 current_ms = ms_min;
             if (ms_min < best_ms) {
@@ -864,7 +870,7 @@ ct_status autotune(ct_ctx *c)
                 best = cfg;
             }
         }
-        if (best_ms > (1.0f - kTuneMargin) * current_ms) best = current;
+        if (!whole_runs && best_ms > (1.0f - kTuneMargin) * current_ms) best = current;
         std::lock_guard<std::mutex> lk(g_tuned_mu);
         store_tune_cache(key, best);
     }
