@@ -356,18 +356,26 @@ def roofline(t, traffic_units=None, traffic_model=None):
                                     "probe of the sweep: 66-69 lane-instructions per CU per clock "
                                     "against 64)",
                             "counted": counted_issue(kps) if newton and traffic_model == "pairs" else None},
-            "limiter": "the per-step chain of each event (its step's items, then the tile "
-                       "updates and the compaction that publish the next step), not the VALU "
-                       "issue rate: on the 8 keV batch a copy of the kernel with half the "
-                       "pair-loop instructions ran no faster, and workgroups wait for work "
-                       "about a fifth of the time"}
+            "limiter": "two bounds that meet on the 8 keV batch: the VALU issue rate (the "
+                       "counters read about 69 lane-instructions per CU per clock over the "
+                       "whole launch, the ceiling a standalone probe of the pair sweep "
+                       "reaches) and the per-step chain of each event (its step's items, then "
+                       "the tile updates and the compaction that publish the next step): a "
+                       "copy of the kernel with half or none of the pair-loop instructions "
+                       "ran no faster"}
 
 
 def plain_rate(ct, torch, sensor, events, prec, max_steps=0):
     """One event at a time (the autotuner's launch for a single event); the
-    first event once untimed (tuning), then all timed."""
+    first event of each hole count once untimed (the autotuner keys its
+    launches by size, so every tuning happens there), then all timed."""
     sim = ct.Simulator(sensor, prec, device=0, options=ct.CT_OPT_AUTOTUNE)
-    simulate(ct, sim, events[0], max_steps)
+    seen = set()
+    for ev in events:
+        n = (int(ev.n_carriers[0]), float(ev.energy_kev[0]))  # <= 0 holes: set by the energy
+        if n not in seen:
+            seen.add(n)
+            simulate(ct, sim, ev, max_steps)
     torch.cuda.synchronize()
     pp, t1 = 0, time.perf_counter()
     for ev in events:
