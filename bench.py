@@ -356,13 +356,13 @@ def roofline(t, traffic_units=None, traffic_model=None):
                                     "probe of the sweep: 66-69 lane-instructions per CU per clock "
                                     "against 64)",
                             "counted": counted_issue(kps) if newton and traffic_model == "pairs" else None},
-            "limiter": "two bounds that meet on the 8 keV batch: the VALU issue rate (the "
-                       "counters read about 69 lane-instructions per CU per clock over the "
-                       "whole launch, the ceiling a standalone probe of the pair sweep "
-                       "reaches) and the per-step chain of each event (its step's items, then "
-                       "the tile updates and the compaction that publish the next step): a "
-                       "copy of the kernel with half or none of the pair-loop instructions "
-                       "ran no faster"}
+            "limiter": "the VALU issue rate (on the 8 keV batch the counters read about 72 "
+                       "lane-instructions per CU per clock over the whole launch, at or above "
+                       "the ceiling a standalone probe of the pair sweep reaches), with the "
+                       "per-step chain of each event (its step's items, then the tile updates "
+                       "and the compaction that publish the next step) about a tenth lower: a "
+                       "copy of the kernel with half the pair-loop instructions ran 11% faster, "
+                       "one with none no faster than that"}
 
 
 def plain_rate(ct, torch, sensor, events, prec, max_steps=0):

@@ -131,6 +131,16 @@ __device__ __forceinline__ void pair_f64(const D4 &s, double s2, const double (&
 #ifndef CT_F32_WAVES_PER_EU
 #define CT_F32_WAVES_PER_EU 8
 #endif
+// The Newton-pair kernel at 7: at 8 the compiler keeps only 72 scalar
+// registers (16 of the SIMD's share are held back for the trap handler) and
+// spills the kernel's uniform values (parameters, pointers, the item's
+// split) into vector lanes, about 1100 lane reads in the item set-up, the
+// update and the compaction; at 7 it has 94 scalar and 72 vector registers,
+// the lane reads halve, and whole runs are 2-5% faster although each SIMD
+// holds one wave fewer.
+#ifndef CT_NEWTON_WAVES_PER_EU
+#define CT_NEWTON_WAVES_PER_EU 7
+#endif
 #ifndef CT_F64_WAVES_PER_EU
 #define CT_F64_WAVES_PER_EU 4
 #endif
@@ -846,10 +856,9 @@ __device__ void run_loop_newton(const DevParams &dp, const DevBatch &bt, const D
     }
 }
 
-// With charges the LDS of 8 workgroups no longer fits a CU: 7 per CU.
+// (With charges the LDS of 8 workgroups would not fit a CU either.)
 template <int BS, bool Q>
-__global__ __launch_bounds__(BS)
-__attribute__((amdgpu_waves_per_eu(Q ? CT_F32_WAVES_PER_EU - 1 : CT_F32_WAVES_PER_EU)))
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(CT_NEWTON_WAVES_PER_EU)))
 void k_run_newton(DevParams dp, DevBatch bt, DevQueue dq, RunArgs ra)
 {
     __shared__ float src[3 * 2 * BS];             // four blocks of 64 sources, each twice
