@@ -356,7 +356,7 @@ def roofline(t, traffic_units=None, traffic_model=None):
                                     "probe of the sweep: 66-69 lane-instructions per CU per clock "
                                     "against 64)",
                             "counted": counted_issue(kps) if newton and traffic_model == "pairs" else None},
-            "limiter": "the VALU issue rate (on the 8 keV batch the counters read about 72 "
+            "limiter": "the VALU issue rate (on the 8 keV batch the counters read about 73 "
                        "lane-instructions per CU per clock over the whole launch, at or above "
                        "the ceiling a standalone probe of the pair sweep reaches), with the "
                        "per-step chain of each event (its step's items, then the tile updates "
