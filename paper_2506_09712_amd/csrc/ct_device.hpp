@@ -86,6 +86,21 @@ __device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMI
 // s_waitcnt vmcnt(0): this thread's vector memory operations have completed.
 __device__ __forceinline__ void wait_own_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// The same kernel argument, read through an index the compiler cannot see is
+// 0.  Called at the top of a persistent loop's body, it makes the compiler
+// load the argument's fields (scalar loads from the argument segment) where
+// the body uses them, instead of keeping all of them in scalar registers from
+// kernel entry on: the run kernels take more uniform values than fit, and the
+// compiler would spill the rest into vector lanes and read each back with one
+// VALU instruction.
+template <class T>
+__device__ __forceinline__ const T &reload_arg(const T &arg)
+{
+    int zero = 0;
+    asm volatile("" : "+s"(zero));
+    return (&arg)[zero];
+}
+
 __device__ __forceinline__ void st_dev(double *p, double v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -229,9 +229,12 @@ __device__ __forceinline__ void set_item_priority(double z_ref, double H)
 }
 
 template <int KT, int BS, bool F32>
-__device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue &dq,
-                         const RunArgs &ra, void *lds)
+__device__ void run_loop(const DevParams &dp_arg, const DevBatch &bt_arg, const DevQueue &dq_arg,
+                         const RunArgs &ra_arg, void *lds)
 {
+    const DevParams &dp = dp_arg;
+    const DevBatch &bt = bt_arg;
+    const DevQueue &dq = dq_arg;
     constexpr int T = KT * BS;
     constexpr int W = BS / 64;
     __shared__ QItem s_item;
@@ -246,6 +249,10 @@ __device__ void run_loop(const DevParams &dp, const DevBatch &bt, const DevQueue
     const bool repulsion = (dp.flags & 1u) != 0;
 
     for (;;) {
+        const DevParams &dp = reload_arg(dp_arg);  // read again in every item
+        const DevBatch &bt = reload_arg(bt_arg);
+        const DevQueue &dq = reload_arg(dq_arg);
+        const RunArgs &ra = reload_arg(ra_arg);
         __syncthreads();  // LDS of the previous item is free
         if (tid == 0) {
             QItem it{};
@@ -600,19 +607,12 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
     const int ctiles = ra.chunk / BS;
 
     for (;;) {
-        // The kernel's arguments are read again from the argument segment in
-        // every item (scalar loads through an index the compiler cannot see
-        // is 0), instead of being held in scalar registers across the whole
-        // loop: there are too many of them, and the compiler would spill them
-        // into vector lanes and read them back with one VALU instruction each
-        // (about 480 fewer such reads in the kernel; whole runs 0.6-1.4%
-        // faster).
-        int zero = 0;
-        asm volatile("" : "+s"(zero));
-        const DevParams &dp = (&dp_arg)[zero];
-        const DevBatch &bt = (&bt_arg)[zero];
-        const DevQueue &dq = (&dq_arg)[zero];
-        const RunArgs &ra = (&ra_arg)[zero];
+        // the arguments are read again in every item (about 480 fewer lane
+        // reads of spilled scalars in the kernel; whole runs 0.6-1.4% faster)
+        const DevParams &dp = reload_arg(dp_arg);
+        const DevBatch &bt = reload_arg(bt_arg);
+        const DevQueue &dq = reload_arg(dq_arg);
+        const RunArgs &ra = reload_arg(ra_arg);
         __syncthreads();  // LDS of the previous item is free
         if (tid == 0) {
             QItem it{};

@@ -318,9 +318,14 @@ __device__ void block_sum4(double (&v)[4], double *red)
 //     then every workgroup forms the same new count and centre (sums in
 //     slice order) and copies its survivors to their packed slots        (barrier)
 // All workgroups of the event run the same number of steps and barriers.
-__device__ void sph_event_group(const DevParams &dp, const DevBatch &bt, const SphArgs &sa,
-                                const SphGroupArgs &ga, int b, int g, int G, const SphShared &sh)
+__device__ void sph_event_group(const DevParams &dp_arg, const DevBatch &bt_arg,
+                                const SphArgs &sa_arg, const SphGroupArgs &ga_arg, int b, int g,
+                                int G, const SphShared &sh)
 {
+    const DevParams &dp = dp_arg;
+    const DevBatch &bt = bt_arg;
+    const SphArgs &sa = sa_arg;
+    const SphGroupArgs &ga = ga_arg;
     constexpr int BS = kSphSharedBlock, W = BS / 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int base = bt.off[b];
@@ -336,6 +341,10 @@ __device__ void sph_event_group(const DevParams &dp, const DevBatch &bt, const S
     int64_t taken = bt.call_steps[b];
     double cx = bt.ref[4 * b + 0], cy = bt.ref[4 * b + 1], cz = bt.ref[4 * b + 2];
     while (n > 0 && (sa.field_only || taken < sa.max_steps)) {
+        const DevParams &dp = reload_arg(dp_arg);  // read again in every step
+        const DevBatch &bt = reload_arg(bt_arg);
+        const SphArgs &sa = reload_arg(sa_arg);
+        const SphGroupArgs &ga = reload_arg(ga_arg);
         const int lo = (int)((int64_t)n * g / G), hi = (int)((int64_t)n * (g + 1) / G);
         double scale = 0.0;
         if (repulsion) {
@@ -519,8 +528,11 @@ __device__ void sph_event_group(const DevParams &dp, const DevBatch &bt, const S
 // batch that one workgroup runs (one workgroup per such event, from the list
 // sa.single), k_sph_shared the events shared by several.
 __global__ __launch_bounds__(kSphBlock) __attribute__((amdgpu_waves_per_eu(4)))
-void k_sph_single(DevParams dp, DevBatch bt, SphArgs sa)
+void k_sph_single(DevParams dp_arg, DevBatch bt_arg, SphArgs sa_arg)
 {
+    const DevParams &dp = dp_arg;
+    const DevBatch &bt = bt_arg;
+    const SphArgs &sa = sa_arg;
     constexpr int BS = kSphBlock, W = BS / 64;
     static_assert(kSphBins % BS == 0, "bins per thread");
     __shared__ int hist[kSphBins];
@@ -538,6 +550,9 @@ void k_sph_single(DevParams dp, DevBatch bt, SphArgs sa)
     int64_t step = bt.ev_step[b];
     int64_t taken = bt.call_steps[b];
     while (n > 0 && (sa.field_only || taken < sa.max_steps)) {
+        const DevParams &dp = reload_arg(dp_arg);  // read again in every step
+        const DevBatch &bt = reload_arg(bt_arg);
+        const SphArgs &sa = reload_arg(sa_arg);
         const double cx = bt.ref[4 * b + 0], cy = bt.ref[4 * b + 1], cz = bt.ref[4 * b + 2];
         const bool small = n <= kSphLdsKeys;
         double scale = 0.0;
