@@ -535,6 +535,46 @@ __device__ __forceinline__ void sweep64(const float *__restrict__ p, const float
     }
 }
 
+// Two targets per lane (t0, t1: the same lane of two target blocks) against
+// one block of 64 sources, laid out and rotated as in sweep64<true>: every
+// source read and every rotation of the reaction registers serves two pair
+// evaluations, 33 VALU instructions per two pairs instead of 36.  Holes only
+// (no charges).
+__device__ __forceinline__ void sweep64x2(const float *__restrict__ p, float s2, float t0x,
+                                          float t0y, float t0z, float t1x, float t1y, float t1z,
+                                          float &a0x, float &a0y, float &a0z, float &a1x,
+                                          float &a1y, float &a1z, float &bx, float &by, float &bz)
+{
+    for (int s0 = 0; s0 < 64; s0 += CT_PAIR_UNROLL) {
+#pragma unroll
+        for (int u = 0; u < CT_PAIR_UNROLL; ++u) {
+            const float *q = p + 3 * (s0 + u);
+            const float qx = q[0], qy = q[1], qz = q[2];
+            const float dx0 = t0x - qx, dy0 = t0y - qy, dz0 = t0z - qz;
+            const float dx1 = t1x - qx, dy1 = t1y - qy, dz1 = t1z - qz;
+            float r0 = fmaf(dx0, dx0, s2);
+            float r1 = fmaf(dx1, dx1, s2);
+            r0 = fmaf(dy0, dy0, r0);
+            r1 = fmaf(dy1, dy1, r1);
+            r0 = fmaf(dz0, dz0, r0);
+            r1 = fmaf(dz1, dz1, r1);
+            const float i0 = __builtin_amdgcn_rsqf(r0);
+            const float i1 = __builtin_amdgcn_rsqf(r1);
+            const float c0 = i0 * i0 * i0;
+            const float c1 = i1 * i1 * i1;
+            a0x = fmaf(dx0, c0, a0x);
+            a0y = fmaf(dy0, c0, a0y);
+            a0z = fmaf(dz0, c0, a0z);
+            a1x = fmaf(dx1, c1, a1x);
+            a1y = fmaf(dy1, c1, a1y);
+            a1z = fmaf(dz1, c1, a1z);
+            bx = lane_up(fmaf(-dx1, c1, fmaf(-dx0, c0, bx)));
+            by = lane_up(fmaf(-dy1, c1, fmaf(-dy0, c0, by)));
+            bz = lane_up(fmaf(-dz1, c1, fmaf(-dz0, c0, bz)));
+        }
+    }
+}
+
 // A wave's 64 targets against the other 63 holes of their own block: lane l
 // meets hole l + s (mod 64) at the offsets s = 1..32, read from p = the
 // block's doubled entries + lane + 1, so that each pair of the block is met
@@ -642,6 +682,18 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
             tz = (float)(bt.cz[base + si] - rz);
         }
         const bool wave_has_targets = a * BS + w * 64 < n;
+        // Partner tiles of the holes-only kernel are swept two targets per
+        // lane: waves w and w ^ 1 both hold target blocks w and w ^ 1, and
+        // split the source blocks between them (w even: 0 and 1; odd: 2 and
+        // 3).  This lane's second target is lane `lane` of block w ^ 1.
+        const int si1 = a * BS + (w ^ 1) * 64 + lane;
+        float ux = 1e18f, uy = 1e18f, uz = 1e18f;
+        if (!Q && si1 < n) {
+            ux = (float)(bt.cx[base + si1] - rx);
+            uy = (float)(bt.cy[base + si1] - ry);
+            uz = (float)(bt.cz[base + si1] - rz);
+        }
+        const bool pair_has_targets = a * BS + (w & ~1) * 64 < n;
         const int o0 = r * sp.C;
         const int o1 = min(o0 + sp.C, sp.newton ? sym_partners(sp.T, a) : sp.T);
         double ex = 0.0, ey = 0.0, ez = 0.0;
@@ -725,6 +777,53 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
                         ey += (double)q[1];
                         ez += (double)q[2];
                     }
+                }
+            } else if (!Q && reacts) {
+                // blocks v = 2 (w & 1) and v + 1 against targets w and w ^ 1;
+                // the sums of target w ^ 1 go to wave w ^ 1 through the two
+                // blocks of this wave's reaction rows it does not use
+                static_assert(W == 4, "four blocks per tile");
+                float cx = 0.0f, cy = 0.0f, cz = 0.0f;
+                for (int k = 0; k < 2; ++k) {
+                    const int v = 2 * (w & 1) + k;
+                    float bx = 0.0f, by = 0.0f, bz = 0.0f;
+                    if (pair_has_targets && v < nblk)
+                        sweep64x2(src + 3 * (v * 128 + lane), dp.s2f, tx, ty, tz, ux, uy, uz, ax,
+                                  ay, az, cx, cy, cz, bx, by, bz);
+                    float *q = react + 3 * (w * BS + v * 64 + lane);
+                    q[0] = bx;
+                    q[1] = by;
+                    q[2] = bz;
+                }
+                {
+                    float *q = react + 3 * (w * BS + (2 - 2 * (w & 1)) * 64 + lane);
+                    q[0] = cx;
+                    q[1] = cy;
+                    q[2] = cz;
+                }
+                __syncthreads();
+                if (sj < n) {
+                    // source block v = tid / 64 was swept by waves v / 2 and
+                    // v / 2 + 2
+                    const int wa = (tid >> 6) >> 1;
+                    const float *q0 = react + 3 * (wa * BS + tid);
+                    const float *q1 = react + 3 * ((wa + 2) * BS + tid);
+                    const double qx = (double)q0[0] + (double)q1[0];
+                    const double qy = (double)q0[1] + (double)q1[1];
+                    const double qz = (double)q0[2] + (double)q1[2];
+                    const int64_t o2 = po + 3 * (int64_t)(sp.R + o - 1) * n0 + sj;
+                    st_dev(&dq.part[o2], qx);
+                    st_dev(&dq.part[o2 + n0], qy);
+                    st_dev(&dq.part[o2 + 2 * n0], qz);
+                }
+                {
+                    // target block w over the other two source blocks, from
+                    // wave w ^ 1
+                    const int wp = w ^ 1;
+                    const float *q = react + 3 * (wp * BS + (2 - 2 * (wp & 1)) * 64 + lane);
+                    ex += (double)q[0];
+                    ey += (double)q[1];
+                    ez += (double)q[2];
                 }
             } else if (reacts) {
                 for (int v = 0; v < W; ++v) {
