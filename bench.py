@@ -61,10 +61,12 @@ VALU_OP_PEAK = VALU_ISSUE_PER_S
 OPS_PER_CARRIER = 72
 FP32_VECTOR_PEAK = 157.3e12   # MI355X FP32 vector FLOP/s (published)
 # VALU lane-instructions per ordered pair in the compiled pair loops (v_rsq_f32
-# included): the Newton-pair sweep issues 145 per 8 unordered pairs (3 sub,
-# 3 FMA, v_rsq, 2 mul, 3 + 3 FMA, 3 DPP lane moves), each serving two ordered
-# pairs; the one-sided loop 96 per 8 ordered pairs.
-NEWTON_INSTR_PER_PAIR = 145 / 16
+# included): the Newton-pair sweep of partner tiles, two targets per lane,
+# issues 265 per 16 unordered pairs (per pair 3 sub, 3 FMA, v_rsq, 2 mul,
+# 3 + 3 FMA, and 3 DPP lane moves per two pairs), each serving two ordered
+# pairs; a tile against itself, one target per lane, 145 per 8 (about a ninth
+# of the pairs of an 8 keV event); the one-sided loop 96 per 8 ordered pairs.
+NEWTON_INSTR_PER_PAIR = 265 / 32
 ONE_SIDED_INSTR_PER_PAIR = 12.0
 # Executed FLOP: 24 per unordered pair (FMA as 2, rsqrt as 1), 12 per ordered.
 NEWTON_EXECUTED_FLOP_PER_PAIR = 12
@@ -356,13 +358,12 @@ def roofline(t, traffic_units=None, traffic_model=None):
                                     "probe of the sweep: 66-69 lane-instructions per CU per clock "
                                     "against 64)",
                             "counted": counted_issue(kps) if newton and traffic_model == "pairs" else None},
-            "limiter": "the VALU issue rate (on the 8 keV batch the counters read about 73 "
-                       "lane-instructions per CU per clock over the whole launch, at or above "
-                       "the ceiling a standalone probe of the pair sweep reaches), with the "
-                       "per-step chain of each event (its step's items, then the tile updates "
-                       "and the compaction that publish the next step) about a tenth lower: a "
-                       "copy of the kernel with half the pair-loop instructions ran 11% faster, "
-                       "one with none no faster than that"}
+            "limiter": "on the 8 keV batch the per-step chain of each event (its step's "
+                       "items, then the tile updates and the compaction that publish the next "
+                       "step), with the VALU issue rate close behind: the kernel issues about 66 "
+                       "lane-instructions per CU per clock, under the ceiling of about 70 that "
+                       "it reached with one target per lane, when a copy with half the "
+                       "pair-loop instructions ran 11% faster and one with none no faster"}
 
 
 def plain_rate(ct, torch, sensor, events, prec, max_steps=0):
