@@ -143,12 +143,15 @@ def sources_digest(model):
     return h.hexdigest()
 
 
-def measured_traffic(model, units_per_launch, chunk_len=None):
+def measured_traffic(model, units_per_launch, chunk_len=None, max_holes=None):
     """HBM bytes per kernel launch from the committed rocprofv3 counter
     summary (bytes per hole update; per event for the generator), or None when
     the kernel's sources have changed since the counters were taken, or (pair
-    kernel) when the launch's source chunk differs from the profiled one: the
-    partial-field traffic grows with the number of chunks."""
+    kernel) when the launch splits the events' steps into other work items
+    than the profiled launches did: the partial-field traffic grows with the
+    number of items.  A tile of the largest event (max_holes) meets at most
+    P = T // 2 + 1 tiles (T its tiles of 256), so every source chunk of P
+    tiles or more gives one item per tile, the same split."""
     path = TRAFFIC_PROFILES[model]
     try:
         text = open(path).read()
@@ -164,6 +167,17 @@ def measured_traffic(model, units_per_launch, chunk_len=None):
         per = vals.get(f"{unit}_chunk{chunk_len}")
         if per is None and int(vals.get("chunk_len", -1)) == chunk_len:
             per = vals.get(unit)
+        if per is None and max_holes:
+            whole = (-(-int(max_holes) // 256) // 2 + 1) * 256
+            if chunk_len >= whole:
+                same = sorted(int(line.split(":")[0][len(unit) + 6:])
+                              for line in text.splitlines()
+                              if line.startswith(f"{unit}_chunk"))
+                same = [c for c in same if c >= whole]
+                if same:
+                    per = dict(line.split(":", 1) for line in text.splitlines()
+                               if line.startswith(f"{unit}_chunk{same[0]}:"))[
+                        f"{unit}_chunk{same[0]}"]
         if per is None:
             return None, f"no counters taken with source chunks of {chunk_len}"
     per = float(per)
@@ -321,7 +335,7 @@ def timed_runs(ct, torch, sensor, batch, steps, warmup, options, launch, label):
     return res
 
 
-def roofline(t, traffic_units=None, traffic_model=None):
+def roofline(t, traffic_units=None, traffic_model=None, max_holes=None):
     """The step kernel against the published FP32 peak (20 flop per ordered
     pair, the N-body convention: a pair-equivalent rate) and against the VALU
     issue rate its compiled pair loop would need (one vector instruction per
@@ -334,7 +348,7 @@ def roofline(t, traffic_units=None, traffic_model=None):
     hps = t["hole_steps_per_run"] / max(t["kernel_launches_per_run"], 1)
     traffic, note = (None, "counters taken on the 8 keV batch only")
     if traffic_model:
-        traffic, note = measured_traffic(traffic_model, hps, t["launch"]["chunk_len"])
+        traffic, note = measured_traffic(traffic_model, hps, t["launch"]["chunk_len"], max_holes)
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
             "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
             "frac_note": "pair-equivalent: 20 flop per ordered pair (N-body convention) against "
@@ -405,7 +419,8 @@ def measure(a, ct, torch, label, sensor, batch, steps, warmup, tune, launch, hea
     t = timed_runs(ct, torch, sensor, batch, steps, warmup, tune, launch,
                    f"{label} fp32-batched" + (", autotuned" if tune else ""))
     res["fp32_batched"] = t
-    res["roofline"] = roofline(t, traffic_model="pairs" if label == "cfg2" else None)
+    res["roofline"] = roofline(t, traffic_model="pairs" if label == "cfg2" else None,
+                               max_holes=int(batch.n_carriers.max()))
     if tune:
         d = timed_runs(ct, torch, sensor, batch, max(1, steps // 2), 1, 0, None,
                        f"{label} fp32-batched, default launch")
