@@ -111,7 +111,7 @@ enum {
                              default as many as make about 6e11 pair evaluations, 2 to 1000; each
                              from the freshly seeded state, the persistent kernel alone) and
                              keep the fastest (when those steps do not finish the batch, only if
-                             it beats the current launch by 1% or more);
+                             it beats the current launch by 3% or more);
                              candidates keep Newton pairs
                              where the context uses them.  The choice is cached per device
                              architecture, compute units, precision, physics switches,

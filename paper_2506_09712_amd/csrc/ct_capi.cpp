@@ -781,7 +781,7 @@ void store_tune_cache(const std::string &key, const ct::LaunchCfg &cfg)  // g_tu
 
 // Least relative gain over the current launch that a candidate timed on a
 // prefix (not on whole runs) must show to replace it.
-constexpr float kTuneMargin = 0.01f;
+constexpr float kTuneMargin = 0.03f;
 
 // Steps of the whole-run prefix each candidate is timed on: CT_TUNE_STEPS,
 // else enough for about 6e11 pair evaluations at the first step's pair
@@ -810,8 +810,8 @@ int64_t tune_steps(const BatchShape &s)
 // (a 60 keV batch's first steps favour shorter chunks that lose over the
 // whole run), so near-ties keep the default.  Candidates keep Newton pairs
 // where the context uses them (FP32, repulsion, CT_OPT_ONE_SIDED unset): one
-// target per thread, blocks of 256, chunks of 1 to 15 tiles.  The state is
-// the seeded one afterwards.
+// target per thread, blocks of 256, chunks of 1 to 15 tiles, each distinct
+// split of the batch timed once.  The state is the seeded one afterwards.
 ct_status autotune(ct_ctx *c)
 {
     const bool newton = resolve_cfg(c, ct::LaunchCfg{1, ct::kSymTile, ct::kSymTile}).newton != 0;
@@ -834,9 +834,16 @@ ct_status autotune(ct_ctx *c)
     ct_status st;
     if (!cached) {
         std::vector<ct::LaunchCfg> cand;
+        // Newton chunks of P tiles or more, P the most tiles a tile of the
+        // largest event meets, all give one item per tile and step: the same
+        // split, timed once (as the shortest of them)
+        const int T = (c->shape.n_max + ct::kSymTile - 1) / ct::kSymTile;
+        const int P = T <= ct::kSymMaxTiles ? T / 2 + 1 : 1 << 30;
+        auto split_of = [&](int chunk) { return std::min(chunk / ct::kSymTile, P); };
         if (newton) {
             for (int chunk : {256, 512, 768, 1024, 1280, 1792, 2304, 3840})
-                cand.push_back(ct::LaunchCfg{1, ct::kSymTile, chunk});
+                if (cand.empty() || split_of(chunk) != split_of(cand.back().chunk))
+                    cand.push_back(ct::LaunchCfg{1, ct::kSymTile, chunk});
         } else {
             cand = {{1, 256, 512}, {1, 256, 768}, {1, 256, 1280}, {1, 256, 2304},
                     {2, 256, 1280}, {1, 128, 256}, {1, 128, 512}};
@@ -863,7 +870,8 @@ ct_status autotune(ct_ctx *c)
                 ms_min = std::min(ms_min, (float)(c->field_ms - before));
             }
             if (c->h_sched->active != 0) whole_runs = false;
-            if (cfg.kt == current.kt && cfg.bs == current.bs && cfg.chunk == current.chunk)
+            if (cfg.kt == current.kt && cfg.bs == current.bs &&
+                (newton ? split_of(cfg.chunk) == split_of(current.chunk) : cfg.chunk == current.chunk))
                 current_ms = ms_min;
             if (ms_min < best_ms) {
                 best_ms = ms_min;
@@ -871,6 +879,9 @@ ct_status autotune(ct_ctx *c)
             }
         }
         if (!whole_runs && best_ms > (1.0f - kTuneMargin) * current_ms) best = current;
+        if (newton && best.kt == current.kt && best.bs == current.bs &&
+            split_of(best.chunk) == split_of(current.chunk))
+            best = current;  // the same split: keep the context's own launch
         std::lock_guard<std::mutex> lk(g_tuned_mu);
         store_tune_cache(key, best);
     }
