@@ -669,6 +669,10 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
         set_item_priority(bt.ref[4 * b + 2], dp.H);
         const SymSplit sp = sym_split(n, ctiles);
         const int64_t po = dq.part_off[b];
+        // partial fields of Newton items are kept in FP32 (the slot array
+        // read as floats, same indices): each is one FP32 rounding of an
+        // FP64 sum of FP32 partials, and the tile adds its slots in FP64
+        float *const pf = reinterpret_cast<float *>(dq.part);
         double rx, ry, rz;
         tile_origin(bt, base + a * BS, rx, ry, rz);
         // targets past the end are parked far away, where every pair term
@@ -812,9 +816,9 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
                     const double qy = (double)q0[1] + (double)q1[1];
                     const double qz = (double)q0[2] + (double)q1[2];
                     const int64_t o2 = po + 3 * (int64_t)(sp.R + o - 1) * n0 + sj;
-                    st_dev(&dq.part[o2], qx);
-                    st_dev(&dq.part[o2 + n0], qy);
-                    st_dev(&dq.part[o2 + 2 * n0], qz);
+                    st_dev(&pf[o2], (float)qx);
+                    st_dev(&pf[o2 + n0], (float)qy);
+                    st_dev(&pf[o2 + 2 * n0], (float)qz);
                 }
                 {
                     // target block w over the other two source blocks, from
@@ -847,9 +851,9 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
                         qz += (double)q[2];
                     }
                     const int64_t o2 = po + 3 * (int64_t)(sp.R + o - 1) * n0 + sj;
-                    st_dev(&dq.part[o2], qx);
-                    st_dev(&dq.part[o2 + n0], qy);
-                    st_dev(&dq.part[o2 + 2 * n0], qz);
+                    st_dev(&pf[o2], (float)qx);
+                    st_dev(&pf[o2 + n0], (float)qy);
+                    st_dev(&pf[o2 + 2 * n0], (float)qz);
                 }
             } else if (wave_has_targets) {
                 float bx = 0.0f, by = 0.0f, bz = 0.0f;
@@ -870,9 +874,9 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
         if (split) {
             if (si < n) {
                 const int64_t o2 = po + 3 * (int64_t)r * n0 + si;
-                st_dev(&dq.part[o2], ex);
-                st_dev(&dq.part[o2 + n0], ey);
-                st_dev(&dq.part[o2 + 2 * n0], ez);
+                st_dev(&pf[o2], (float)ex);
+                st_dev(&pf[o2 + n0], (float)ey);
+                st_dev(&pf[o2 + 2 * n0], (float)ez);
             }
             wait_own_stores();
             __syncthreads();
@@ -905,9 +909,9 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
                     fx = fy = fz = 0.0;
                     for (int k2 = 0; k2 < nslot; ++k2) {
                         const int64_t o2 = po + 3 * (int64_t)k2 * n0 + s;
-                        fx += dq.part[o2];
-                        fy += dq.part[o2 + n0];
-                        fz += dq.part[o2 + 2 * n0];
+                        fx += (double)pf[o2];
+                        fy += (double)pf[o2 + n0];
+                        fz += (double)pf[o2 + 2 * n0];
                     }
                 }
                 field_or_advance(dp, bt, b, base + s, dp.K * fx, dp.K * fy, dp.K * fz,
