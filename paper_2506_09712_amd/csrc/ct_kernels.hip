@@ -503,13 +503,13 @@ __device__ __forceinline__ float lane_up(float v)
 // With Q (holes and electrons), pq holds the sources' charges (+1 / -1) at
 // the entries of p, and qi is the target's: the target receives q_j times the
 // pair term, the source minus q_i times it.
-template <bool REACT, bool Q>
+template <bool REACT, bool Q, int STEPS = 64>
 __device__ __forceinline__ void sweep64(const float *__restrict__ p, const float *__restrict__ pq,
                                         float s2, float tx, float ty, float tz, float qi,
                                         float &ax, float &ay, float &az, float &bx, float &by,
                                         float &bz)
 {
-    for (int s0 = 0; s0 < 64; s0 += CT_PAIR_UNROLL) {
+    for (int s0 = 0; s0 < STEPS; s0 += CT_PAIR_UNROLL) {
 #pragma unroll
         for (int u = 0; u < CT_PAIR_UNROLL; ++u) {
             const float *q = p + 3 * (s0 + u);
@@ -747,9 +747,12 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
             const int nblk = min(W, (n - pt * BS + 63) / 64);  // blocks holding holes
             float ax = 0.0f, ay = 0.0f, az = 0.0f;
             if (sp.newton && o == 0) {
-                // the tile with itself: block pairs (w, w), (w, w + 1) and, for
-                // w < 2, (w, w + 2) (mod 4) meet every pair of the tile once;
-                // the reactions land on this tile's own holes
+                // the tile with itself, 128 steps per wave: block w with
+                // itself (offsets 1 to 32), block pair (w, w + 1), and half
+                // of (w, w + 2): waves 0 and 1 take its offsets 0 to 31 from
+                // block w's side, waves 2 and 3 the rest from the other
+                // side (offsets 1 to 32 of (w, w - 2)); the reactions land on
+                // this tile's own holes
                 static_assert(W == 4, "four blocks per tile");
                 {
                     float bx = 0.0f, by = 0.0f, bz = 0.0f;
@@ -761,16 +764,35 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
                     q[1] = by;
                     q[2] = bz;
                 }
-                for (int k = 1; k < W; ++k) {
-                    const int v = (w + k) & (W - 1);
+                {
+                    const int v = (w + 1) & (W - 1);
                     float bx = 0.0f, by = 0.0f, bz = 0.0f;
-                    if ((k == 1 || (k == 2 && w < 2)) && wave_has_targets && v < nblk)
+                    if (wave_has_targets && v < nblk)
                         sweep64<true, Q>(src + 3 * (v * 128 + lane), sq + v * 128 + lane, dp.s2f, tx,
                                          ty, tz, qi, ax, ay, az, bx, by, bz);
                     float *q = react + 3 * (w * BS + v * 64 + lane);
                     q[0] = bx;
                     q[1] = by;
                     q[2] = bz;
+                }
+                {
+                    const int v = (w + 2) & (W - 1);
+                    const int off = w < 2 ? 0 : 1;  // first offset of this wave's half
+                    float bx = 0.0f, by = 0.0f, bz = 0.0f;
+                    if (wave_has_targets && v < nblk)
+                        sweep64<true, Q, 32>(src + 3 * (v * 128 + lane + off), sq + v * 128 + lane + off,
+                                             dp.s2f, tx, ty, tz, qi, ax, ay, az, bx, by, bz);
+                    // after 32 rotations lane l holds source l + off + 32
+                    float *q = react + 3 * (w * BS + v * 64 + ((lane + off + 32) & 63));
+                    q[0] = bx;
+                    q[1] = by;
+                    q[2] = bz;
+                }
+                {
+                    float *q = react + 3 * (w * BS + ((w + 3) & (W - 1)) * 64 + lane);
+                    q[0] = 0.0f;
+                    q[1] = 0.0f;
+                    q[2] = 0.0f;
                 }
                 __syncthreads();
                 if (si < n) {
