@@ -374,7 +374,7 @@ def roofline(t, traffic_units=None, traffic_model=None, max_holes=None):
                             "counted": counted_issue(kps) if newton and traffic_model == "pairs" else None},
             "limiter": "on the 8 keV batch the per-step chain of each event (its step's "
                        "items, then the tile updates and the compaction that publish the next "
-                       "step), with the VALU issue rate close behind: the kernel issues about 66 "
+                       "step), with the VALU issue rate close behind: the kernel issues about 67 "
                        "lane-instructions per CU per clock, under the ceiling of about 70 that "
                        "it reached with one target per lane, when a copy with half the "
                        "pair-loop instructions ran 11% faster and one with none no faster"}
