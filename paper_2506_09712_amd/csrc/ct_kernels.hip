@@ -538,12 +538,15 @@ __device__ __forceinline__ void sweep64(const float *__restrict__ p, const float
 // Two targets per lane (t0, t1: the same lane of two target blocks) against
 // one block of 64 sources, laid out and rotated as in sweep64<true>: every
 // source read and every rotation of the reaction registers serves two pair
-// evaluations, 33 VALU instructions per two pairs instead of 36.  Holes only
-// (no charges).
-__device__ __forceinline__ void sweep64x2(const float *__restrict__ p, float s2, float t0x,
-                                          float t0y, float t0z, float t1x, float t1y, float t1z,
-                                          float &a0x, float &a0y, float &a0z, float &a1x,
-                                          float &a1y, float &a1z, float &bx, float &by, float &bz)
+// evaluations, 33 VALU instructions per two pairs instead of 36 (holes
+// only).  With Q the charges enter as in sweep64: the targets receive q_j
+// times the pair term, the source minus q_i0 and q_i1 times theirs.
+template <bool Q>
+__device__ __forceinline__ void sweep64x2(const float *__restrict__ p, const float *__restrict__ pq,
+                                          float s2, float t0x, float t0y, float t0z, float t1x,
+                                          float t1y, float t1z, float qi0, float qi1, float &a0x,
+                                          float &a0y, float &a0z, float &a1x, float &a1y,
+                                          float &a1z, float &bx, float &by, float &bz)
 {
     for (int s0 = 0; s0 < 64; s0 += CT_PAIR_UNROLL) {
 #pragma unroll
@@ -562,15 +565,18 @@ __device__ __forceinline__ void sweep64x2(const float *__restrict__ p, float s2,
             const float i1 = __builtin_amdgcn_rsqf(r1);
             const float c0 = i0 * i0 * i0;
             const float c1 = i1 * i1 * i1;
-            a0x = fmaf(dx0, c0, a0x);
-            a0y = fmaf(dy0, c0, a0y);
-            a0z = fmaf(dz0, c0, a0z);
-            a1x = fmaf(dx1, c1, a1x);
-            a1y = fmaf(dy1, c1, a1y);
-            a1z = fmaf(dz1, c1, a1z);
-            bx = lane_up(fmaf(-dx1, c1, fmaf(-dx0, c0, bx)));
-            by = lane_up(fmaf(-dy1, c1, fmaf(-dy0, c0, by)));
-            bz = lane_up(fmaf(-dz1, c1, fmaf(-dz0, c0, bz)));
+            const float qs = Q ? pq[s0 + u] : 1.0f;
+            const float g0 = Q ? c0 * qs : c0, g1 = Q ? c1 * qs : c1;  // target sides
+            const float h0 = Q ? c0 * qi0 : c0, h1 = Q ? c1 * qi1 : c1;  // source side
+            a0x = fmaf(dx0, g0, a0x);
+            a0y = fmaf(dy0, g0, a0y);
+            a0z = fmaf(dz0, g0, a0z);
+            a1x = fmaf(dx1, g1, a1x);
+            a1y = fmaf(dy1, g1, a1y);
+            a1z = fmaf(dz1, g1, a1z);
+            bx = lane_up(fmaf(-dx1, h1, fmaf(-dx0, h0, bx)));
+            by = lane_up(fmaf(-dy1, h1, fmaf(-dy0, h0, by)));
+            bz = lane_up(fmaf(-dz1, h1, fmaf(-dz0, h0, bz)));
         }
     }
 }
@@ -686,13 +692,14 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
             tz = (float)(bt.cz[base + si] - rz);
         }
         const bool wave_has_targets = a * BS + w * 64 < n;
-        // Partner tiles of the holes-only kernel are swept two targets per
-        // lane: waves w and w ^ 1 both hold target blocks w and w ^ 1, and
-        // split the source blocks between them (w even: 0 and 1; odd: 2 and
-        // 3).  This lane's second target is lane `lane` of block w ^ 1.
+        // Partner tiles are swept two targets per lane: waves w and w ^ 1
+        // both hold target blocks w and w ^ 1, and split the source blocks
+        // between them (w even: 0 and 1; odd: 2 and 3).  This lane's second
+        // target is lane `lane` of block w ^ 1.
         const int si1 = a * BS + (w ^ 1) * 64 + lane;
         float ux = 1e18f, uy = 1e18f, uz = 1e18f;
-        if (!Q && si1 < n) {
+        const float qi1 = si1 < nh ? 1.0f : (si1 < n ? -1.0f : 0.0f);
+        if (si1 < n) {
             ux = (float)(bt.cx[base + si1] - rx);
             uy = (float)(bt.cy[base + si1] - ry);
             uz = (float)(bt.cz[base + si1] - rz);
@@ -804,7 +811,7 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
                         ez += (double)q[2];
                     }
                 }
-            } else if (!Q && reacts) {
+            } else if (reacts) {
                 // blocks v = 2 (w & 1) and v + 1 against targets w and w ^ 1;
                 // the sums of target w ^ 1 go to wave w ^ 1 through the two
                 // blocks of this wave's reaction rows it does not use
@@ -814,8 +821,8 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
                     const int v = 2 * (w & 1) + k;
                     float bx = 0.0f, by = 0.0f, bz = 0.0f;
                     if (pair_has_targets && v < nblk)
-                        sweep64x2(src + 3 * (v * 128 + lane), dp.s2f, tx, ty, tz, ux, uy, uz, ax,
-                                  ay, az, cx, cy, cz, bx, by, bz);
+                        sweep64x2<Q>(src + 3 * (v * 128 + lane), sq + v * 128 + lane, dp.s2f, tx, ty,
+                                     tz, ux, uy, uz, qi, qi1, ax, ay, az, cx, cy, cz, bx, by, bz);
                     float *q = react + 3 * (w * BS + v * 64 + lane);
                     q[0] = bx;
                     q[1] = by;
@@ -850,32 +857,6 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
                     ex += (double)q[0];
                     ey += (double)q[1];
                     ez += (double)q[2];
-                }
-            } else if (reacts) {
-                for (int v = 0; v < W; ++v) {
-                    float bx = 0.0f, by = 0.0f, bz = 0.0f;
-                    if (wave_has_targets && v < nblk)
-                        sweep64<true, Q>(src + 3 * (v * 128 + lane), sq + v * 128 + lane, dp.s2f, tx,
-                                         ty, tz, qi, ax, ay, az, bx, by, bz);
-                    float *q = react + 3 * (w * BS + v * 64 + lane);
-                    q[0] = bx;
-                    q[1] = by;
-                    q[2] = bz;
-                }
-                __syncthreads();
-                if (sj < n) {
-                    double qx = 0.0, qy = 0.0, qz = 0.0;
-#pragma unroll
-                    for (int w2 = 0; w2 < W; ++w2) {
-                        const float *q = react + 3 * (w2 * BS + tid);
-                        qx += (double)q[0];
-                        qy += (double)q[1];
-                        qz += (double)q[2];
-                    }
-                    const int64_t o2 = po + 3 * (int64_t)(sp.R + o - 1) * n0 + sj;
-                    st_dev(&pf[o2], (float)qx);
-                    st_dev(&pf[o2 + n0], (float)qy);
-                    st_dev(&pf[o2 + 2 * n0], (float)qz);
                 }
             } else if (wave_has_targets) {
                 float bx = 0.0f, by = 0.0f, bz = 0.0f;
