@@ -110,9 +110,9 @@ enum {
                              steps of the seeded batch (environment variable CT_TUNE_STEPS, by
                              default as many as make about 6e11 pair evaluations, 2 to 1000; each
                              from the freshly seeded state, the persistent kernel alone) and
-                             keep the fastest (when those steps do not finish the batch, only if
-                             it beats the current launch by 3% or more);
-                             candidates keep Newton pairs
+                             keep the fastest if it beats the current launch by 1% or more
+                             (3% when those steps do not finish the batch); candidates keep
+                             Newton pairs
                              where the context uses them.  The choice is cached per device
                              architecture, compute units, precision, physics switches,
                              CT_OPT_ONE_SIDED and batch shape (events, largest event, total

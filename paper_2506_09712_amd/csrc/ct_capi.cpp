@@ -779,9 +779,11 @@ void store_tune_cache(const std::string &key, const ct::LaunchCfg &cfg)  // g_tu
     }
 }
 
-// Least relative gain over the current launch that a candidate timed on a
-// prefix (not on whole runs) must show to replace it.
+// Least relative gain over the current launch that a candidate must show to
+// replace it: timed on a prefix of the runs, or on whole runs (there only
+// run-to-run noise, a few tenths of a percent, has to be outweighed).
 constexpr float kTuneMargin = 0.03f;
+constexpr float kTuneMarginWhole = 0.01f;
 
 // Steps of the whole-run prefix each candidate is timed on: CT_TUNE_STEPS,
 // else enough for about 6e11 pair evaluations at the first step's pair
@@ -804,11 +806,11 @@ int64_t tune_steps(const BatchShape &s)
 // launch (the persistent kernel only, HIP events; the best of three runs,
 // each from the freshly seeded state) and keep the fastest.  Every candidate
 // runs the same steps of the same events, so the fastest prefix is the one
-// with the highest pair rate.  When the steps timed did not finish the
-// batch, the fastest must beat the context's current launch by kTuneMargin:
-// a prefix does not rank launches whose whole runs differ by less than that
-// (a 60 keV batch's first steps favour shorter chunks that lose over the
-// whole run), so near-ties keep the default.  Candidates keep Newton pairs
+// with the highest pair rate.  The fastest must beat the context's current
+// launch by kTuneMarginWhole when the timed steps finished the batch, by
+// kTuneMargin when they did not: a prefix does not rank launches whose
+// whole runs differ by less than that (a 60 keV batch's first steps favour
+// shorter chunks that lose over the whole run).  Near-ties keep the default.  Candidates keep Newton pairs
 // where the context uses them (FP32, repulsion, CT_OPT_ONE_SIDED unset): one
 // target per thread, blocks of 256, chunks of 1 to 15 tiles, each distinct
 // split of the batch timed once.  The state is the seeded one afterwards.
@@ -878,7 +880,8 @@ ct_status autotune(ct_ctx *c)
                 best = cfg;
             }
         }
-        if (!whole_runs && best_ms > (1.0f - kTuneMargin) * current_ms) best = current;
+        if (best_ms > (1.0f - (whole_runs ? kTuneMarginWhole : kTuneMargin)) * current_ms)
+            best = current;
         if (newton && best.kt == current.kt && best.bs == current.bs &&
             split_of(best.chunk) == split_of(current.chunk))
             best = current;  // the same split: keep the context's own launch
