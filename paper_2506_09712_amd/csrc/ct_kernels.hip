@@ -622,14 +622,17 @@ constexpr int kMaxTouch = kSymMaxC + 1;
 // target per thread, tiles of kSymTile; the split is described with
 // sym_split; with Q the events hold holes and electrons, whose charges are
 // staged beside the sources).  An item stages each partner tile in LDS as
-// four doubled blocks of 64; every wave sweeps its 64 targets over them.
-// The reactions of the four waves are summed per source in wave order (FP64)
-// into the partner's partial slot; the target side folds each partner
-// tile's FP32 sum into FP64 and goes to the item's own slot.  Each item then
-// counts down the tiles it contributed to; the workgroup that completes a
-// tile sums its slots in slot order and updates it, and the one that
-// completes the event's last tile compacts the event and queues its next
-// step, as in run_loop.
+// four doubled blocks of 64.  Against itself the tile is swept one target
+// per lane, 128 steps per wave; against a partner tile waves w and w ^ 1
+// each sweep two of the four source blocks with two targets per lane
+// (blocks w and w ^ 1).  The reactions on a source are summed over the
+// waves that met it, in wave order (FP64), into the partner's partial slot;
+// the target side folds each partner tile's FP32 sums into FP64 and goes to
+// the item's own slot (slots hold FP32).  Each item then counts down the
+// tiles it contributed to; the workgroup that completes a tile sums its
+// slots in slot order and updates it, and the one that completes the
+// event's last tile compacts the event and queues its next step, as in
+// run_loop.
 template <int BS, bool Q>
 __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
                                 const DevQueue &dq_arg, const RunArgs &ra_arg, float *src,
