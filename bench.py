@@ -61,12 +61,12 @@ VALU_OP_PEAK = VALU_ISSUE_PER_S
 OPS_PER_CARRIER = 72
 FP32_VECTOR_PEAK = 157.3e12   # MI355X FP32 vector FLOP/s (published)
 # VALU lane-instructions per ordered pair in the compiled pair loops (v_rsq_f32
-# included): the Newton-pair sweep of partner tiles, two targets per lane,
-# issues 265 per 16 unordered pairs (per pair 3 sub, 3 FMA, v_rsq, 2 mul,
-# 3 + 3 FMA, and 3 DPP lane moves per two pairs), each serving two ordered
+# included): the Newton-pair sweep of partner tiles, four targets per lane,
+# issues 253 per 16 unordered pairs (per pair 3 sub, 3 FMA, v_rsq, 2 mul,
+# 3 + 3 FMA, and 3 DPP lane moves per four pairs), each serving two ordered
 # pairs; a tile against itself, one target per lane, 145 per 8 (about a ninth
 # of the pairs of an 8 keV event); the one-sided loop 96 per 8 ordered pairs.
-NEWTON_INSTR_PER_PAIR = 265 / 32
+NEWTON_INSTR_PER_PAIR = 253 / 32
 ONE_SIDED_INSTR_PER_PAIR = 12.0
 # Executed FLOP: 24 per unordered pair (FMA as 2, rsqrt as 1), 12 per ordered.
 NEWTON_EXECUTED_FLOP_PER_PAIR = 12

@@ -538,9 +538,9 @@ __device__ __forceinline__ void sweep64(const float *__restrict__ p, const float
 // Two targets per lane (t0, t1: the same lane of two target blocks) against
 // one block of 64 sources, laid out and rotated as in sweep64<true>: every
 // source read and every rotation of the reaction registers serves two pair
-// evaluations, 33 VALU instructions per two pairs instead of 36 (holes
-// only).  With Q the charges enter as in sweep64: the targets receive q_j
-// times the pair term, the source minus q_i0 and q_i1 times theirs.
+// evaluations.  The charged kernel's partner sweep: the targets receive q_j
+// times the pair term, the source minus q_i0 and q_i1 times theirs (four
+// targets per lane, as in the holes-only kernel, spill registers there).
 template <bool Q>
 __device__ __forceinline__ void sweep64x2(const float *__restrict__ p, const float *__restrict__ pq,
                                           float s2, float t0x, float t0y, float t0z, float t1x,
@@ -577,6 +577,47 @@ __device__ __forceinline__ void sweep64x2(const float *__restrict__ p, const flo
             bx = lane_up(fmaf(-dx1, h1, fmaf(-dx0, h0, bx)));
             by = lane_up(fmaf(-dy1, h1, fmaf(-dy0, h0, by)));
             bz = lane_up(fmaf(-dz1, h1, fmaf(-dz0, h0, bz)));
+        }
+    }
+}
+
+// Four targets per lane (lane l of each of the tile's four target blocks)
+// against one block of 64 sources, laid out and rotated as in sweep64<true>:
+// every source read and every rotation of the reaction registers serves four
+// pair evaluations, 63 VALU instructions per four pairs (holes only).  With
+// Q the charges enter as in sweep64.
+template <bool Q>
+__device__ __forceinline__ void sweep64x4(const float *__restrict__ p, const float *__restrict__ pq,
+                                          float s2, const float (&t)[4][3], const float (&qt)[4],
+                                          float (&acc)[4][3], float &bx, float &by, float &bz)
+{
+    // 4 steps (16 evaluations) per iteration: at 8 the loop spills a register
+    for (int s0 = 0; s0 < 64; s0 += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float *q = p + 3 * (s0 + u);
+            const float qx = q[0], qy = q[1], qz = q[2];
+            const float qs = Q ? pq[s0 + u] : 1.0f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float dx = t[k][0] - qx, dy = t[k][1] - qy, dz = t[k][2] - qz;
+                float r2 = fmaf(dx, dx, s2);
+                r2 = fmaf(dy, dy, r2);
+                r2 = fmaf(dz, dz, r2);
+                const float i1 = __builtin_amdgcn_rsqf(r2);
+                const float c = i1 * i1 * i1;
+                const float g = Q ? c * qs : c;     // target side
+                const float h = Q ? c * qt[k] : c;  // source side
+                acc[k][0] = fmaf(dx, g, acc[k][0]);
+                acc[k][1] = fmaf(dy, g, acc[k][1]);
+                acc[k][2] = fmaf(dz, g, acc[k][2]);
+                bx = fmaf(-dx, h, bx);
+                by = fmaf(-dy, h, by);
+                bz = fmaf(-dz, h, bz);
+            }
+            bx = lane_up(bx);
+            by = lane_up(by);
+            bz = lane_up(bz);
         }
     }
 }
@@ -695,19 +736,33 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
             tz = (float)(bt.cz[base + si] - rz);
         }
         const bool wave_has_targets = a * BS + w * 64 < n;
-        // Partner tiles are swept two targets per lane: waves w and w ^ 1
-        // both hold target blocks w and w ^ 1, and split the source blocks
-        // between them (w even: 0 and 1; odd: 2 and 3).  This lane's second
-        // target is lane `lane` of block w ^ 1.
+        // Partner tiles are swept four targets per lane: every wave holds
+        // lane `lane` of the four target blocks, and wave w sweeps source
+        // block w of the partner tile.  (The charged kernel sweeps two per
+        // lane: waves w and w ^ 1 hold blocks w and w ^ 1 and split the
+        // source blocks, w even taking 0 and 1; its second target is lane
+        // `lane` of block w ^ 1.)
         const int si1 = a * BS + (w ^ 1) * 64 + lane;
         float ux = 1e18f, uy = 1e18f, uz = 1e18f;
         const float qi1 = si1 < nh ? 1.0f : (si1 < n ? -1.0f : 0.0f);
-        if (si1 < n) {
+        if (Q && si1 < n) {
             ux = (float)(bt.cx[base + si1] - rx);
             uy = (float)(bt.cy[base + si1] - ry);
             uz = (float)(bt.cz[base + si1] - rz);
         }
         const bool pair_has_targets = a * BS + (w & ~1) * 64 < n;
+        float t4[4][3], q4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int sk = a * BS + k * 64 + lane;
+            q4[k] = sk < nh ? 1.0f : (sk < n ? -1.0f : 0.0f);
+            t4[k][0] = t4[k][1] = t4[k][2] = 1e18f;
+            if (!Q && sk < n) {
+                t4[k][0] = (float)(bt.cx[base + sk] - rx);
+                t4[k][1] = (float)(bt.cy[base + sk] - ry);
+                t4[k][2] = (float)(bt.cz[base + sk] - rz);
+            }
+        }
         const int o0 = r * sp.C;
         const int o1 = min(o0 + sp.C, sp.newton ? sym_partners(sp.T, a) : sp.T);
         double ex = 0.0, ey = 0.0, ez = 0.0;
@@ -813,6 +868,39 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
                         ey += (double)q[1];
                         ez += (double)q[2];
                     }
+                }
+            } else if (!Q && reacts) {
+                // source block w against all four target blocks; this lane
+                // ends with the reaction on source w * 64 + lane, which is
+                // this thread's sj, and the target sums go to their threads
+                // through the reaction rows
+                static_assert(W == 4, "four blocks per tile");
+                float acc[4][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f},
+                                   {0.0f, 0.0f, 0.0f}};
+                float bx = 0.0f, by = 0.0f, bz = 0.0f;
+                if (w < nblk)
+                    sweep64x4<Q>(src + 3 * (w * 128 + lane), sq + w * 128 + lane, dp.s2f, t4, q4, acc,
+                                 bx, by, bz);
+                if (sj < n) {
+                    const int64_t o2 = po + 3 * (int64_t)(sp.R + o - 1) * n0 + sj;
+                    st_dev(&pf[o2], bx);
+                    st_dev(&pf[o2 + n0], by);
+                    st_dev(&pf[o2 + 2 * n0], bz);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    float *q = react + 3 * (w * BS + k * 64 + lane);
+                    q[0] = acc[k][0];
+                    q[1] = acc[k][1];
+                    q[2] = acc[k][2];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int w2 = 0; w2 < W; ++w2) {
+                    const float *q = react + 3 * (w2 * BS + tid);
+                    ex += (double)q[0];
+                    ey += (double)q[1];
+                    ez += (double)q[2];
                 }
             } else if (reacts) {
                 // blocks v = 2 (w & 1) and v + 1 against targets w and w ^ 1;
