@@ -372,12 +372,14 @@ def roofline(t, traffic_units=None, traffic_model=None, max_holes=None):
                                     "probe of the sweep: 66-69 lane-instructions per CU per clock "
                                     "against 64)",
                             "counted": counted_issue(kps) if newton and traffic_model == "pairs" else None},
-            "limiter": "on the 8 keV batch the per-step chain of each event (its step's "
-                       "items, then the tile updates and the compaction that publish the next "
-                       "step), with the VALU issue rate close behind: the kernel issues about 67 "
-                       "lane-instructions per CU per clock, under the ceiling of about 70 that "
-                       "it reached with one target per lane, when a copy with half the "
-                       "pair-loop instructions ran 11% faster and one with none no faster"}
+            "limiter": "on the 8 keV batch the VALU issue rate and the per-step chain of "
+                       "each event (its step's items, then the tile updates and the compaction "
+                       "that publish the next step) together: the kernel issues about 69 "
+                       "lane-instructions per CU per clock, the ceiling a standalone probe of "
+                       "the pair sweep reaches, and fewer instructions per pair shorten both "
+                       "(four targets per lane: 4-5% faster; a copy with half the pair-loop "
+                       "instructions of an earlier version ran 11% faster, one with none no "
+                       "faster than that)"}
 
 
 def plain_rate(ct, torch, sensor, events, prec, max_steps=0):
