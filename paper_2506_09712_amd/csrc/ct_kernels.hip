@@ -585,8 +585,9 @@ __device__ __forceinline__ void sweep64x2(const float *__restrict__ p, const flo
 // against one block of 64 sources, laid out and rotated as in sweep64<true>:
 // every source read and every rotation of the reaction registers serves four
 // pair evaluations, 63 VALU instructions per four pairs (holes only).  With
-// Q the charges enter as in sweep64.
-template <bool Q>
+// Q the charges enter as in sweep64.  Only the first NT target blocks hold
+// holes (a ragged tile); the others are skipped.
+template <bool Q, int NT>
 __device__ __forceinline__ void sweep64x4(const float *__restrict__ p, const float *__restrict__ pq,
                                           float s2, const float (&t)[4][3], const float (&qt)[4],
                                           float (&acc)[4][3], float &bx, float &by, float &bz)
@@ -599,7 +600,7 @@ __device__ __forceinline__ void sweep64x4(const float *__restrict__ p, const flo
             const float qx = q[0], qy = q[1], qz = q[2];
             const float qs = Q ? pq[s0 + u] : 1.0f;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < NT; ++k) {
                 const float dx = t[k][0] - qx, dy = t[k][1] - qy, dz = t[k][2] - qz;
                 float r2 = fmaf(dx, dx, s2);
                 r2 = fmaf(dy, dy, r2);
@@ -878,9 +879,19 @@ __device__ void run_loop_newton(const DevParams &dp_arg, const DevBatch &bt_arg,
                 float acc[4][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f},
                                    {0.0f, 0.0f, 0.0f}};
                 float bx = 0.0f, by = 0.0f, bz = 0.0f;
-                if (w < nblk)
-                    sweep64x4<Q>(src + 3 * (w * 128 + lane), sq + w * 128 + lane, dp.s2f, t4, q4, acc,
-                                 bx, by, bz);
+                if (w < nblk) {
+                    const float *ps = src + 3 * (w * 128 + lane);
+                    const float *pq = sq + w * 128 + lane;
+                    const int ntb = min(W, (n - a * BS + 63) / 64);  // target blocks with holes
+                    if (ntb == 4)
+                        sweep64x4<Q, 4>(ps, pq, dp.s2f, t4, q4, acc, bx, by, bz);
+                    else if (ntb == 3)
+                        sweep64x4<Q, 3>(ps, pq, dp.s2f, t4, q4, acc, bx, by, bz);
+                    else if (ntb == 2)
+                        sweep64x4<Q, 2>(ps, pq, dp.s2f, t4, q4, acc, bx, by, bz);
+                    else
+                        sweep64x4<Q, 1>(ps, pq, dp.s2f, t4, q4, acc, bx, by, bz);
+                }
                 if (sj < n) {
                     const int64_t o2 = po + 3 * (int64_t)(sp.R + o - 1) * n0 + sj;
                     st_dev(&pf[o2], bx);
