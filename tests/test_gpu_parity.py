@@ -157,7 +157,10 @@ def field_error_bound(xyz, soft, K, fp32, tile=256, frame_tile=256):
     return bound
 
 
-@pytest.mark.parametrize("n", [1, 2, 7, 255, 256, 257, 1000, 2222])
+# sizes whose last tile holds 1, 2 (356, 384), 3 (700, 2222) and 4 (1000)
+# blocks of 64 holes, even and odd tile counts (1800: 8 tiles), so that the
+# Newton kernel's partner sweep meets every count of occupied target blocks
+@pytest.mark.parametrize("n", [1, 2, 7, 255, 256, 257, 356, 384, 700, 1000, 1800, 2222])
 @pytest.mark.parametrize("prec", [FP64, FP32])
 def test_field_matches_oracle(ct, n, prec):
     rng = np.random.default_rng(n)
